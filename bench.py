@@ -1,0 +1,153 @@
+"""Benchmark of block-parallel FSR on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Workload: one 1920x1080 synthetic frame, quarter-sampling mask, B = 4, L = 14
+(32 x 32 support and DFT), I = 100 iterations, rho = 0.7, gamma = 0.5:
+129,600 independent blocks.  One step reconstructs the whole frame (gather,
+weighting, forward DFTs, I greedy iterations, target inverse DFT, compose)
+with inputs already resident in device memory.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "reconstructed Mpixel/s + p99 frame latency, served/batched vs plain, PSNR gap≤0.05dB"
+WORKLOAD = "fhd_quarter"
+PEAK_FP32_TFLOPS = 157.3       # MI355X FP32 vector peak (256 CU x 2.4 GHz x 256 flop/clk)
+
+
+def algorithmic_flops_per_block(S: int, B: int, iters: int) -> float:
+    """Flops the method itself requires per block (stated in the design notes):
+    12 S^2 per iteration (objective 4, residual complex update 8), the two real
+    forward DFTs at the radix-2 count 2 * 2.5 S^2 log2(S^2), and 4 B^2 per
+    iteration for the target model."""
+    return 12.0 * S * S * iters + 5.0 * S * S * math.log2(S * S) + 4.0 * B * B * iters
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-blocks", type=int, default=32000,
+                    help="blocks in the oracle's timed sample")
+    return ap.parse_args()
+
+
+def cpu_baseline(img32, mask, w, n_blocks_sample):
+    import oracle
+    threads = len(os.sched_getaffinity(0))
+    rng = np.random.default_rng(12345)
+    ids = np.sort(rng.choice(w.n_blocks, size=min(n_blocks_sample, w.n_blocks), replace=False))
+    img64 = img32.astype(np.float64)
+    oracle.reconstruct_blocks(img64, mask, ids[:64], w.iterations, threads=threads)  # warm
+    t0 = time.perf_counter()
+    oracle.reconstruct_blocks(img64, mask, ids, w.iterations, threads=threads)
+    dt = time.perf_counter() - t0
+    px = len(ids) * w.block * w.block
+    return {"value": px / dt / 1e6, "unit": "Mpixel/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(ids)} seeded random blocks ({px} pixels) of the same frame, "
+                      f"FP64 C oracle, OpenMP over blocks, {dt:.2f} s wall"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(multi-GPU sharding is described in the design notes only)"}))
+        sys.exit(2)
+    import torch
+
+    import paper_2202_13926_amd as fsr
+    import synth
+
+    w = synth.workload(WORKLOAD)
+    img, mask = w.inputs()
+    img32 = img.astype(np.float32)
+    dev = torch.device("cuda:0")
+    ti = torch.from_numpy(img32).to(dev)
+    tm = torch.from_numpy(mask).to(dev)
+    out = torch.empty_like(ti)
+    ctx = fsr.Context(0)
+    params = fsr.make_params(block=w.block, border=w.border, iterations=w.iterations, rho=w.rho,
+                             gamma=w.gamma)
+    stream = torch.cuda.current_stream(dev)
+
+    for _ in range(args.warmup):
+        fsr.fsr_reconstruct(ctx, ti, tm, out, params, None, stream)
+    torch.cuda.synchronize()
+
+    K = args.steps
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for i in range(K):
+        fsr.fsr_reconstruct(ctx, ti, tm, out, params, None, stream)
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(K)])   # ms, device clock
+    total_ms = ev[0].elapsed_time(ev[K])
+    ms_per_step = total_ms / K
+    pixels = w.height * w.width
+    value = pixels / (ms_per_step * 1e-3) / 1e6
+
+    flops = algorithmic_flops_per_block(w.support, w.block, w.iterations) * w.n_blocks
+    achieved = flops / (ms_per_step * 1e-3) / 1e12
+
+    # quality of this run (vs. the ground-truth frame)
+    g = out.cpu().numpy()
+    from synth.metrics import psnr
+    quality = {"psnr_db": round(psnr(img32, g), 4),
+               "psnr_missing_db": round(psnr(img32, g, mask == 0), 4)}
+
+    res = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded generator standing in for the paper's photographs)",
+        "config": {"workload": "fhd_quarter: 1920x1080 frame, quarter-sampling mask, B=4 L=14 "
+                               "(S=32), I=100, rho=0.7, gamma=0.5, plain one-launch path",
+                   "blocks": w.n_blocks, "pixels": pixels, "path": "fsr_reconstruct"},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 5),
+                       "p99": round(float(np.percentile(lat, 99)), 5),
+                       "max": round(float(lat.max()), 5)},
+        "wall_s": round(wall, 4),
+        "quality": quality,
+        "roofline": {"bound": "alu", "kernel": "fsr_plain_s32",
+                     "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                     "algorithmic_flop_per_launch": flops,
+                     "avg_launch_ms": round(ms_per_step, 5),
+                     "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(img32, mask, w, args.cpu_blocks)
+    ctx.close()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

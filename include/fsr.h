@@ -1,0 +1,134 @@
+/*
+ * fsr.h -- C ABI of libfsr, block-parallel Frequency Selective Reconstruction
+ * (FSR) on AMD Instinct MI355X (gfx950).
+ *
+ * FSR (Regensky et al., MMSP 2020, Sec. II) fills the missing pixels of an
+ * image sampled under a sparse, non-regular mask.  The image is cut into
+ * B x B target blocks; each block plus an L-pixel border (an S x S support,
+ * S = B + 2L) is modelled independently as a sparse sum of 2D-DFT basis
+ * images, grown greedily in the frequency domain: per iteration an argmax of
+ * the frequency-weighted residual energy (Eq. 8), a relaxed projection
+ * coefficient (Eqs. 10-11) and a subtraction of the shifted weight spectrum
+ * from the residual (Eq. 12).  Unknown target pixels take the real part of
+ * the model's inverse DFT; known pixels are copied.
+ *
+ * Conventions shared by every entry point:
+ *   - Images are float32 gray values (any scale; the paper's is [0, 255]),
+ *     row-major with a row stride in elements.  Masks are uint8, same shape
+ *     and stride, nonzero = known.  Pixels outside the image are unknown.
+ *   - All image, mask, output and log pointers are DEVICE pointers owned by
+ *     the caller.  The library never frees them.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Calls
+ *     that take a stream are asynchronous with respect to the host; faults of
+ *     the work they enqueue surface at a later call or synchronisation.
+ *   - Every function returns an fsr_status.  Invalid arguments are detected
+ *     on the host before anything is enqueued and leave all outputs
+ *     untouched.  fsr_last_error_message() describes the last failure of the
+ *     calling thread.  No exception and no abort crosses this interface.
+ *   - The DFT convention is forward unnormalised with exp(-j 2 pi (km+ln)/S)
+ *     (k pairs with rows); argmax ties go to the smaller bin index k*S + l.
+ */
+#ifndef FSR_H
+#define FSR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define FSR_API __attribute__((visibility("default")))
+#else
+#define FSR_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum fsr_status {
+    FSR_OK = 0,
+    FSR_ERR_INVALID_ARG = 1,   /* a pointer, size or parameter is invalid  */
+    FSR_ERR_UNSUPPORTED = 2,   /* valid, but outside what this build runs  */
+    FSR_ERR_OUT_OF_MEMORY = 3, /* a device or host allocation failed       */
+    FSR_ERR_BUDGET = 4,        /* request exceeds the configured budget    */
+    FSR_ERR_HIP = 5,           /* the HIP runtime reported an error        */
+    FSR_ERR_TIMEOUT = 6,       /* a wait ran out of time                   */
+    FSR_ERR_NOT_READY = 7      /* polled work has not finished yet         */
+} fsr_status;
+
+/* How the forward block DFTs are computed. */
+enum {
+    FSR_DFT_FP32 = 0,        /* FP32 in-register FFT on the vector ALUs    */
+    FSR_DFT_SPLIT_BF16 = 1   /* hi+lo bf16 DFT-matrix products on MFMA     */
+};
+
+/*
+ * Method parameters (Sec. II; the paper's defaults B = 4, rho = 0.7,
+ * gamma = 0.5 are Sec. IV's).  Validated before any launch:
+ *   block >= 1, border >= 0, S = block + 2*border even and <= 32,
+ *   iterations >= 0, 0 < rho <= 1, 0 < gamma <= 1 (Sec. II), flags == 0.
+ * This build runs S = 32 with block <= 8 (FSR_ERR_UNSUPPORTED otherwise).
+ */
+typedef struct fsr_params {
+    int32_t block;       /* B: target block edge in pixels                  */
+    int32_t border;      /* L: border on each side of the target            */
+    int32_t iterations;  /* I: fixed number of greedy iterations            */
+    float rho;           /* spatial decay factor of the weight, Eq. 5       */
+    float gamma;         /* orthogonality deficiency compensation, Eq. 11   */
+    int32_t dft;         /* FSR_DFT_*                                       */
+    uint32_t flags;      /* reserved, must be 0                             */
+} fsr_params;
+
+typedef struct fsr_context fsr_context;
+
+/* Library version as major*10000 + minor*100 + patch. */
+FSR_API int32_t fsr_version(void);
+
+/* Human-readable name of a status code (static storage). */
+FSR_API const char *fsr_status_string(fsr_status status);
+
+/* Message of the calling thread's last failure ("" if none; thread-local,
+ * valid until the thread's next failing call). */
+FSR_API const char *fsr_last_error_message(void);
+
+/* Fills *params with B = 4, L = 14, I = 100, rho = 0.7, gamma = 0.5, FP32 DFT. */
+FSR_API fsr_status fsr_params_default(fsr_params *params);
+
+/* Checks a parameter set without touching any device (see fsr_params). */
+FSR_API fsr_status fsr_params_validate(const fsr_params *params);
+
+/* Number of target blocks of a height x width image, ceil(Y/B) * ceil(X/B)
+ * (Eq. 13); -1 if an argument is not positive. */
+FSR_API int64_t fsr_num_blocks(int32_t height, int32_t width, int32_t block);
+
+/*
+ * Creates a context on HIP device `device`: device-resident weight and
+ * frequency tables (per support size and rho, built on first use) and the
+ * tuning state of the batched path.  A context may be used from one thread
+ * at a time (or with external synchronisation).  The caller's current device
+ * is restored before returning.
+ */
+FSR_API fsr_status fsr_context_create(fsr_context **out, int32_t device);
+FSR_API fsr_status fsr_context_destroy(fsr_context *ctx);
+
+/*
+ * Reconstructs one image (Sec. II; one wavefront per block, Sec. III-A).
+ *   image, mask  height x width, row stride `stride` elements (>= width)
+ *   out          height x width, row stride `stride`; every pixel is
+ *                written: known pixels bit-exactly copied from `image`,
+ *                unknown ones set to the real part of the block model
+ *                (unclipped; 0 for a block whose support has no known
+ *                pixel).  Must not overlap `image` or `mask`.
+ *   argmax_log   NULL, or N x I uint16 (N = fsr_num_blocks): the bin
+ *                u*S + v chosen by each block at each iteration, block-major;
+ *                0xFFFF for every iteration of a block without known pixels.
+ * Asynchronous on `stream`.
+ */
+FSR_API fsr_status fsr_reconstruct(fsr_context *ctx, const float *image, const uint8_t *mask,
+                           float *out, int32_t height, int32_t width, int64_t stride,
+                           const fsr_params *params, uint16_t *argmax_log, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FSR_H */

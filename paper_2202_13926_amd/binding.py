@@ -1,0 +1,219 @@
+"""ctypes binding of libfsr (include/fsr.h): argument marshalling only.
+
+Every step of the reconstruction runs in the HIP kernels of libfsr.so; this
+module checks tensor shapes, dtypes and devices, passes raw device pointers
+and the current HIP stream, and turns status codes into exceptions.  If the
+library is missing it raises instead of computing anything itself.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libfsr.so")
+HEADER = os.path.join(os.path.dirname(PKG), "include", "fsr.h")
+
+FSR_OK = 0
+FSR_ERR_INVALID_ARG = 1
+FSR_ERR_UNSUPPORTED = 2
+FSR_ERR_OUT_OF_MEMORY = 3
+FSR_ERR_BUDGET = 4
+FSR_ERR_HIP = 5
+FSR_ERR_TIMEOUT = 6
+FSR_ERR_NOT_READY = 7
+
+FSR_DFT_FP32 = 0
+FSR_DFT_SPLIT_BF16 = 1
+
+
+class FsrError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{status_name(status)}: {message}")
+        self.status = status
+
+
+class fsr_params(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("border", ctypes.c_int32),
+                ("iterations", ctypes.c_int32), ("rho", ctypes.c_float),
+                ("gamma", ctypes.c_float), ("dft", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+def make_params(block=4, border=14, iterations=100, rho=0.7, gamma=0.5, dft=FSR_DFT_FP32,
+                flags=0) -> fsr_params:
+    return fsr_params(block, border, iterations, rho, gamma, dft, flags)
+
+
+_lib = None
+
+
+def declared_functions() -> list[str]:
+    """Names of the functions include/fsr.h declares."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^FSR_API\s+[^;(]*?\b(fsr_\w+)\s*\(", text, flags=re.M)))
+
+
+def load_library(path: str | None = None):
+    """Load libfsr.so (built in-tree by ``python -m paper_2202_13926_amd.build``)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise FsrError(FSR_ERR_UNSUPPORTED,
+                       f"{p} is missing: build it with `python -m paper_2202_13926_amd.build`")
+    lib = ctypes.CDLL(p)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    P = ctypes.POINTER(fsr_params)
+    sig = {
+        "fsr_version": (i32, []),
+        "fsr_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "fsr_last_error_message": (ctypes.c_char_p, []),
+        "fsr_params_default": (ctypes.c_int, [P]),
+        "fsr_params_validate": (ctypes.c_int, [P]),
+        "fsr_num_blocks": (i64, [i32, i32, i32]),
+        "fsr_context_create": (ctypes.c_int, [ctypes.POINTER(vp), i32]),
+        "fsr_context_destroy": (ctypes.c_int, [vp]),
+        "fsr_reconstruct": (ctypes.c_int, [vp, vp, vp, vp, i32, i32, i64, P, vp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def status_name(status: int) -> str:
+    try:
+        return load_library().fsr_status_string(status).decode()
+    except Exception:  # the library may be what is missing
+        return f"status {status}"
+
+
+def _check(status: int):
+    if status != FSR_OK:
+        msg = load_library().fsr_last_error_message().decode()
+        raise FsrError(status, msg)
+
+
+# ---------------------------------------------------------------- plain calls
+def fsr_version() -> int:
+    return int(load_library().fsr_version())
+
+
+def fsr_params_default() -> fsr_params:
+    p = fsr_params()
+    _check(load_library().fsr_params_default(ctypes.byref(p)))
+    return p
+
+
+def fsr_params_validate(params: fsr_params) -> None:
+    _check(load_library().fsr_params_validate(ctypes.byref(params)))
+
+
+def fsr_num_blocks(height: int, width: int, block: int) -> int:
+    return int(load_library().fsr_num_blocks(height, width, block))
+
+
+class Context:
+    """Owns an fsr_context on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        self._ptr = ctypes.c_void_p()
+        _check(load_library().fsr_context_create(ctypes.byref(self._ptr), int(device)))
+        self.device = int(device)
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if not self._ptr:
+            raise FsrError(FSR_ERR_INVALID_ARG, "context is closed")
+        return self._ptr
+
+    def close(self):
+        if self._ptr:
+            load_library().fsr_context_destroy(self._ptr)
+            self._ptr = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fsr_context_create(device: int = 0) -> Context:
+    return Context(device)
+
+
+def fsr_context_destroy(ctx: Context) -> None:
+    ctx.close()
+
+
+def _stream_handle(stream, device):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _image_args(image, mask, out):
+    import torch
+    if image.dtype != torch.float32 or out.dtype != torch.float32:
+        raise FsrError(FSR_ERR_INVALID_ARG, "image and out must be float32")
+    if mask.dtype != torch.uint8:
+        raise FsrError(FSR_ERR_INVALID_ARG, "mask must be uint8")
+    if image.dim() != 2 or mask.shape != image.shape or out.shape != image.shape:
+        raise FsrError(FSR_ERR_INVALID_ARG, "image, mask and out must be 2-D of equal shape")
+    if not (image.is_cuda and mask.is_cuda and out.is_cuda):
+        raise FsrError(FSR_ERR_INVALID_ARG, "image, mask and out must be device tensors")
+    if not (image.device == mask.device == out.device):
+        raise FsrError(FSR_ERR_INVALID_ARG, "image, mask and out must be on one device")
+    strides = {t.stride() for t in (image, mask, out)}
+    if len(strides) != 1 or image.stride(1) != 1:
+        raise FsrError(FSR_ERR_INVALID_ARG, "image, mask and out need unit column stride and one row stride")
+    return image.shape[0], image.shape[1], image.stride(0)
+
+
+def fsr_reconstruct(ctx: Context, image, mask, out, params: fsr_params, argmax_log=None,
+                    stream=None) -> None:
+    """Enqueue one reconstruction on ``stream`` (default: torch's current stream)."""
+    import torch
+    H, W, stride = _image_args(image, mask, out)
+    log_ptr = None
+    if argmax_log is not None:
+        n = fsr_num_blocks(H, W, params.block)
+        if (argmax_log.dtype not in (torch.int16, torch.uint16) or not argmax_log.is_cuda
+                or argmax_log.numel() < n * params.iterations or not argmax_log.is_contiguous()):
+            raise FsrError(FSR_ERR_INVALID_ARG, "argmax_log must be a contiguous 16-bit device tensor of N*I entries")
+        log_ptr = ctypes.c_void_p(argmax_log.data_ptr())
+    _check(load_library().fsr_reconstruct(
+        ctx.handle, ctypes.c_void_p(image.data_ptr()), ctypes.c_void_p(mask.data_ptr()),
+        ctypes.c_void_p(out.data_ptr()), H, W, stride, ctypes.byref(params), log_ptr,
+        _stream_handle(stream, image.device)))
+
+
+def reconstruct(image, mask, params: fsr_params | None = None, ctx: Context | None = None,
+                log: bool = False, stream=None):
+    """Allocate the output (and the argmax log) and run :func:`fsr_reconstruct`.
+    Returns ``out`` or ``(out, log)`` with ``log`` of shape (N, I) int16."""
+    import torch
+    params = params or make_params()
+    ctx = ctx or Context(image.device.index or 0)
+    out = torch.empty_like(image)
+    lg = None
+    if log:
+        n = fsr_num_blocks(image.shape[0], image.shape[1], params.block)
+        lg = torch.empty((n, max(params.iterations, 1)), dtype=torch.int16, device=image.device)
+    fsr_reconstruct(ctx, image, mask, out, params, lg, stream)
+    if log:
+        return out, lg[:, :params.iterations]
+    return out

@@ -1,0 +1,292 @@
+// fsr_api.cpp -- host side of the C ABI declared in include/fsr.h.
+//
+// Argument validation happens before any HIP call so that invalid calls are
+// rejected on machines without a GPU and leave every output untouched.
+#include "fsr.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fsr_internal.h"
+#include "fsr_runtime.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+fsr_status fail(fsr_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+}  // namespace
+
+namespace fsr {
+
+fsr_status set_error(fsr_status st, const char* msg) {
+    g_last_error = msg;
+    return st;
+}
+
+fsr_status hip_fail(hipError_t e, const char* what) {
+    return fail(FSR_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+DeviceGuard::DeviceGuard(int device) {
+    if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
+    if (prev_ != device) {
+        err_ = hipSetDevice(device);
+        changed_ = err_ == hipSuccess;
+    }
+}
+
+DeviceGuard::~DeviceGuard() {
+    if (changed_ && prev_ >= 0) (void)hipSetDevice(prev_);
+}
+
+fsr_status validate_params(const fsr_params* p) {
+    if (!p) return fail(FSR_ERR_INVALID_ARG, "params is NULL");
+    if (p->block < 1) return fail(FSR_ERR_INVALID_ARG, "block must be >= 1 (got %d)", p->block);
+    if (p->border < 0) return fail(FSR_ERR_INVALID_ARG, "border must be >= 0 (got %d)", p->border);
+    const int64_t S = (int64_t)p->block + 2 * (int64_t)p->border;
+    if (S > 32 || S % 2 != 0)
+        return fail(FSR_ERR_INVALID_ARG, "support B + 2L = %lld must be even and <= 32", (long long)S);
+    if (p->iterations < 0)
+        return fail(FSR_ERR_INVALID_ARG, "iterations must be >= 0 (got %d)", p->iterations);
+    if (!(p->rho > 0.0f && p->rho <= 1.0f))
+        return fail(FSR_ERR_INVALID_ARG, "rho must lie in (0, 1] (got %g)", (double)p->rho);
+    if (!(p->gamma > 0.0f && p->gamma <= 1.0f))
+        return fail(FSR_ERR_INVALID_ARG, "gamma must lie in (0, 1] (got %g)", (double)p->gamma);
+    if (p->dft != FSR_DFT_FP32 && p->dft != FSR_DFT_SPLIT_BF16)
+        return fail(FSR_ERR_INVALID_ARG, "unknown dft mode %d", p->dft);
+    if (p->flags != 0) return fail(FSR_ERR_INVALID_ARG, "flags must be 0 (got 0x%x)", p->flags);
+    return FSR_OK;
+}
+
+fsr_status check_supported(const fsr_params* p) {
+    const int S = p->block + 2 * p->border;
+    if (S != kS) return fail(FSR_ERR_UNSUPPORTED, "this build runs support size 32 only (got %d)", S);
+    if (p->block > 8) return fail(FSR_ERR_UNSUPPORTED, "this build runs block <= 8 (got %d)", p->block);
+    return FSR_OK;
+}
+
+static bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
+    const char* pa = (const char*)a;
+    const char* pb = (const char*)b;
+    return pa < pb + nb && pb < pa + na;
+}
+
+fsr_status validate_image(const float* image, const uint8_t* mask, const float* out, int32_t height,
+                          int32_t width, int64_t stride, int32_t block) {
+    if (!image || !mask || !out) return fail(FSR_ERR_INVALID_ARG, "image, mask and out must be non-NULL");
+    if (height < 1 || width < 1)
+        return fail(FSR_ERR_INVALID_ARG, "image size must be positive (got %d x %d)", height, width);
+    if (stride < width)
+        return fail(FSR_ERR_INVALID_ARG, "stride %lld is smaller than width %d", (long long)stride, width);
+    if (stride > (int64_t(1) << 40) / height) return fail(FSR_ERR_INVALID_ARG, "image too large");
+    const int64_t n_blocks = fsr_num_blocks(height, width, block);
+    if (n_blocks > 0x7fffffff) return fail(FSR_ERR_UNSUPPORTED, "more than 2^31-1 blocks");
+    const size_t extent = (size_t)((int64_t)(height - 1) * stride + width);
+    if (ranges_overlap(out, extent * sizeof(float), image, extent * sizeof(float)) ||
+        ranges_overlap(out, extent * sizeof(float), mask, extent))
+        return fail(FSR_ERR_INVALID_ARG, "out must not overlap image or mask");
+    return FSR_OK;
+}
+
+// ---------------------------------------------------------------- tables
+// Spatial weight rho^dist from the support centre (S-1)/2 (Eq. 5, before
+// masking) and frequency weight w_f (Eq. 9), evaluated in double and rounded
+// once to float.
+static std::vector<float> host_rho_pow(float rho) {
+    std::vector<float> t(kBins);
+    const double c = 0.5 * (kS - 1);
+    for (int m = 0; m < kS; ++m)
+        for (int n = 0; n < kS; ++n) {
+            const double d = std::sqrt((m - c) * (m - c) + (n - c) * (n - c));
+            t[m * kS + n] = (float)std::pow((double)rho, d);
+        }
+    return t;
+}
+
+static std::vector<float> host_freq_w() {
+    std::vector<float> t(kBins);
+    const double half = 0.5 * kS;
+    for (int k = 0; k < kS; ++k)
+        for (int l = 0; l < kS; ++l) {
+            const double kt = half - std::fabs(k - half), lt = half - std::fabs(l - half);
+            const double a = 1.0 - std::sqrt(2.0) * std::sqrt((kt * kt + lt * lt) / (double)(kS * kS));
+            t[k * kS + l] = (float)(a * a);
+        }
+    return t;
+}
+
+}  // namespace fsr
+
+using namespace fsr;
+
+struct fsr_context {
+    int device = 0;
+    std::mutex mu;
+    float* freq_w = nullptr;
+    std::map<uint32_t, float*> rho_pow;   // keyed by the bits of rho
+    fsr::BatchState batch;
+};
+
+namespace fsr {
+
+fsr_status context_tables(fsr_context* ctx, float rho, BlockTables* out) {
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    if (!ctx->freq_w) {
+        std::vector<float> h = host_freq_w();
+        float* d = nullptr;
+        hipError_t e = hipMalloc(&d, h.size() * sizeof(float));
+        if (e != hipSuccess) return fail(FSR_ERR_OUT_OF_MEMORY, "hipMalloc(freq table): %s", hipGetErrorString(e));
+        e = hipMemcpy(d, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(d);
+            return hip_fail(e, "upload of frequency table");
+        }
+        ctx->freq_w = d;
+    }
+    uint32_t key;
+    std::memcpy(&key, &rho, sizeof key);
+    auto it = ctx->rho_pow.find(key);
+    if (it == ctx->rho_pow.end()) {
+        std::vector<float> h = host_rho_pow(rho);
+        float* d = nullptr;
+        hipError_t e = hipMalloc(&d, h.size() * sizeof(float));
+        if (e != hipSuccess) return fail(FSR_ERR_OUT_OF_MEMORY, "hipMalloc(weight table): %s", hipGetErrorString(e));
+        e = hipMemcpy(d, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(d);
+            return hip_fail(e, "upload of weight table");
+        }
+        it = ctx->rho_pow.emplace(key, d).first;
+    }
+    out->rho_pow = it->second;
+    out->freq_w = ctx->freq_w;
+    return FSR_OK;
+}
+
+int context_device(const fsr_context* ctx) { return ctx->device; }
+BatchState& context_batch(fsr_context* ctx) { return ctx->batch; }
+std::mutex& context_mutex(fsr_context* ctx) { return ctx->mu; }
+
+}  // namespace fsr
+
+extern "C" {
+
+int32_t fsr_version(void) { return 100; }
+
+const char* fsr_status_string(fsr_status s) {
+    switch (s) {
+    case FSR_OK: return "FSR_OK";
+    case FSR_ERR_INVALID_ARG: return "FSR_ERR_INVALID_ARG";
+    case FSR_ERR_UNSUPPORTED: return "FSR_ERR_UNSUPPORTED";
+    case FSR_ERR_OUT_OF_MEMORY: return "FSR_ERR_OUT_OF_MEMORY";
+    case FSR_ERR_BUDGET: return "FSR_ERR_BUDGET";
+    case FSR_ERR_HIP: return "FSR_ERR_HIP";
+    case FSR_ERR_TIMEOUT: return "FSR_ERR_TIMEOUT";
+    case FSR_ERR_NOT_READY: return "FSR_ERR_NOT_READY";
+    }
+    return "FSR_ERR_UNKNOWN";
+}
+
+const char* fsr_last_error_message(void) { return g_last_error.c_str(); }
+
+fsr_status fsr_params_default(fsr_params* p) {
+    if (!p) return fail(FSR_ERR_INVALID_ARG, "params is NULL");
+    p->block = 4;
+    p->border = 14;
+    p->iterations = 100;
+    p->rho = 0.7f;
+    p->gamma = 0.5f;
+    p->dft = FSR_DFT_FP32;
+    p->flags = 0;
+    return FSR_OK;
+}
+
+fsr_status fsr_params_validate(const fsr_params* p) { return validate_params(p); }
+
+int64_t fsr_num_blocks(int32_t height, int32_t width, int32_t block) {
+    if (height < 1 || width < 1 || block < 1) return -1;
+    return (int64_t)((height + block - 1) / block) * (int64_t)((width + block - 1) / block);
+}
+
+fsr_status fsr_context_create(fsr_context** out, int32_t device) {
+    if (!out) return fail(FSR_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= n)
+        return fail(FSR_ERR_INVALID_ARG, "device %d out of range (%d devices)", device, n);
+    fsr_context* ctx = new (std::nothrow) fsr_context();
+    if (!ctx) return fail(FSR_ERR_OUT_OF_MEMORY, "context allocation failed");
+    ctx->device = device;
+    *out = ctx;
+    return FSR_OK;
+}
+
+fsr_status fsr_context_destroy(fsr_context* ctx) {
+    if (!ctx) return FSR_OK;
+    {
+        DeviceGuard g(ctx->device);
+        release_batch_state(ctx->batch);
+        if (ctx->freq_w) (void)hipFree(ctx->freq_w);
+        for (auto& kv : ctx->rho_pow) (void)hipFree(kv.second);
+    }
+    delete ctx;
+    return FSR_OK;
+}
+
+fsr_status fsr_reconstruct(fsr_context* ctx, const float* image, const uint8_t* mask, float* out,
+                           int32_t height, int32_t width, int64_t stride, const fsr_params* params,
+                           uint16_t* argmax_log, void* stream) {
+    if (!ctx) return fail(FSR_ERR_INVALID_ARG, "context is NULL");
+    fsr_status st = validate_params(params);
+    if (st != FSR_OK) return st;
+    if ((st = check_supported(params)) != FSR_OK) return st;
+    if ((st = validate_image(image, mask, out, height, width, stride, params->block)) != FSR_OK)
+        return st;
+    if (params->dft != FSR_DFT_FP32)
+        return fail(FSR_ERR_UNSUPPORTED, "fsr_reconstruct runs the FP32 DFT; use the batched path for split-bf16");
+
+    DeviceGuard g(ctx->device);
+    if (g.error() != hipSuccess) return hip_fail(g.error(), "hipSetDevice");
+    PlainLaunch p{};
+    if ((st = context_tables(ctx, params->rho, &p.tab)) != FSR_OK) return st;
+    p.img.image = image;
+    p.img.mask = mask;
+    p.img.out = out;
+    p.img.argmax_log = argmax_log;
+    p.img.height = height;
+    p.img.width = width;
+    p.img.stride = stride;
+    p.img.iterations = params->iterations;
+    p.img.nbx = (width + params->block - 1) / params->block;
+    p.img.block_begin = 0;
+    p.block = params->block;
+    p.border = params->border;
+    p.gamma = params->gamma;
+    p.n_blocks = fsr_num_blocks(height, width, params->block);
+    hipError_t e = launch_plain(p, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "launch of the reconstruction kernel");
+    return FSR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,231 @@
+// fsr_block.h -- one support block of FSR on one wavefront (S = 32).
+//
+// Steps (Regensky et al., Sec. II and III-A):
+//   gather     support tile at (by*B - L, bx*B - L); pixels outside the image
+//              or masked out are unknown: f~ = 0, w = 0            (Eqs. 2, 5)
+//   DFT        R_w = DFT2(f~ w), W = DFT2(w): in-register FFTs along the
+//              slot axis, LDS transposes between the passes, then exact
+//              Hermitian symmetrisation X <- (X + conj X[-k]) / 2   (Eq. 7)
+//   loop       I times: objective w_f |R_w|^2 (Eq. 16), wave argmax with
+//              ties to the smaller bin, p = R_w[u,v] / W[0,0] (Eq. 10), model
+//              update accumulated directly into the target pixels (Eq. 11
+//              followed by the inverse DFT restricted to the target), residual
+//              update R_w -= gamma p W[k-u, l-v] with cyclic indices
+//              (Eqs. 12, 14-15)
+//   compose    known target pixels copied, unknown ones take Re g
+//
+// LDS: 16 KiB per wavefront.  The weight spectrum W is stored with its 32
+// rows duplicated (64 rows x 32 bins x float2) so that the rows a lane needs
+// for its 16 bins, (k - u) mod 32 for k = 2s + h, form one contiguous run and
+// every slot's address is the lane's base plus an immediate offset.  The
+// same buffer first serves as the transpose scratch of the DFTs.
+#pragma once
+
+#include "fsr_device.h"
+#include "fsr_internal.h"
+
+namespace fsr {
+
+constexpr int kLdsFloats = 2 * 64 * kS;   // 4096 floats = 16 KiB
+
+// Transpose scratch: two planes (re, im) of 32 rows x kPitch floats.
+__device__ __forceinline__ float* plane_re(float* lds) { return lds; }
+__device__ __forceinline__ float* plane_im(float* lds) { return lds + kS * kPitch; }
+
+// 2D DFT of the real tile v (spatial layout) into the bin layout, exactly
+// Hermitian.  Leaves (re, im) of bins 64*s + lane in (xr, xi).
+__device__ __forceinline__ void dft2_real_to_bins(float (&xr)[16], float (&xi)[16], float* lds,
+                                                  int lane) {
+    const int c = lane & 31, h = lane >> 5;
+    float* pr = plane_re(lds);
+    float* pi = plane_im(lds);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) xi[s] = 0.0f;
+    // pass 1: along m (rows of the tile) for every column n = c
+    dft32_lane_pair(xr, xi, h);                 // slot k' -> bin row k = k' + 16h, column n = c
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        pr[(k + 16 * h) * kPitch + c] = xr[k];
+        pi[(k + 16 * h) * kPitch + c] = xi[k];
+    }
+    __syncthreads();
+    // pass 2: along n for every k = c; slot s takes n = 2s + h
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        xr[s] = pr[c * kPitch + 2 * s + h];
+        xi[s] = pi[c * kPitch + 2 * s + h];
+    }
+    __syncthreads();
+    dft32_lane_pair(xr, xi, h);                 // slot l' -> (k = c, l = l' + 16h)
+#pragma unroll
+    for (int l = 0; l < 16; ++l) {
+        pr[c * kPitch + l + 16 * h] = xr[l];
+        pi[c * kPitch + l + 16 * h] = xi[l];
+    }
+    __syncthreads();
+    // bin layout with exact Hermitian symmetrisation: (k, l) = (2s + h, c)
+    const int lm = (kS - c) & 31;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const int k = 2 * s + h, km = (kS - k) & 31;
+        const float ar = pr[k * kPitch + c], ai = pi[k * kPitch + c];
+        const float br = pr[km * kPitch + lm], bi = pi[km * kPitch + lm];
+        xr[s] = 0.5f * (ar + br);
+        xi[s] = 0.5f * (ai - bi);
+    }
+    __syncthreads();
+}
+
+// Everything a block needs to know about its image and the method.
+struct BlockJob {
+    const float* image;
+    const uint8_t* mask;
+    float* out;
+    uint16_t* log;          // this block's I log entries, or nullptr
+    int32_t height, width;
+    int64_t stride;
+    int32_t by, bx;
+    int32_t iterations;
+};
+
+__device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int L, float gamma,
+                                                  const BlockTables& tab, float* lds) {
+    const int lane = threadIdx.x & 63;
+    const int c = lane & 31, h = lane >> 5;
+    const int y0 = jb.by * B - L, x0 = jb.bx * B - L;
+
+    // ---- gather and weighting (pixel (m, n) = (2s + h, c))
+    float xr[16], wr[16];   // f~ first, then (f~ - mu) w
+    uint64_t any_known = 0;
+    const int x = x0 + c;
+    const bool xin = (unsigned)x < (unsigned)jb.width;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const int m = 2 * s + h, y = y0 + m;
+        const bool in = xin && (unsigned)y < (unsigned)jb.height;
+        // out-of-image lanes load pixel 0 (always valid) and discard it
+        const int64_t off = in ? (int64_t)y * jb.stride + x : 0;
+        const uint8_t kraw = jb.mask[off];
+        const float fraw = jb.image[off];
+        const float rp = tab.rho_pow[m * kS + c];
+        const uint8_t k = in ? kraw : (uint8_t)0;
+        const float f = fraw;
+        const float w = k ? rp : 0.0f;
+        any_known |= ballot(k != 0);
+        xr[s] = k ? f : 0.0f;
+        wr[s] = w;
+    }
+
+    // ---- target pixel owned by this lane (lanes 0 .. B*B-1)
+    const int ti = lane / B, tj = lane - (lane / B) * B;
+    const int tm = L + ti, tn = L + tj;
+    float acc = 0.0f;
+    const int iters = jb.iterations;
+
+    if (any_known != 0) {
+        // ---- forward DFTs (R in registers, W to LDS).  R_w = DFT2(f~ w) is
+        // evaluated as mu W + DFT2((f~ - mu) w) with mu the weighted mean of
+        // the known support pixels: the same value in exact arithmetic, but
+        // the rounding error of the large mean component becomes a multiple
+        // of the very W that the iterations subtract, and the transformed
+        // remainder is small.
+        float sx = 0.0f, sw = 0.0f;
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            sx = fmaf(xr[s], wr[s], sx);
+            sw += wr[s];
+        }
+        sx = wave_sum_f32(sx);
+        sw = wave_sum_f32(sw);
+        const float mu = sw > 0.0f ? sx / sw : 0.0f;
+#pragma unroll
+        for (int s = 0; s < 16; ++s) xr[s] = (xr[s] - mu) * wr[s];
+        float xi[16], wi[16];
+        dft2_real_to_bins(xr, xi, lds, lane);
+        dft2_real_to_bins(wr, wi, lds, lane);
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            xr[s] = fmaf(mu, wr[s], xr[s]);
+            xi[s] = fmaf(mu, wi[s], xi[s]);
+        }
+        float2* wtab = reinterpret_cast<float2*>(lds);
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const int k = 2 * s + h;
+            wtab[k * kS + c] = make_float2(wr[s], wi[s]);
+            wtab[(k + kS) * kS + c] = make_float2(wr[s], wi[s]);
+        }
+        const float w00 = readlane_f(wr[0], 0);
+        const float gi = w00 > 0.0f ? gamma / w00 : 0.0f;
+        float wf[16];
+#pragma unroll
+        for (int s = 0; s < 16; ++s) wf[s] = tab.freq_w[(2 * s + h) * kS + c];
+        // lane i of tw_re/tw_im holds t32[i & 31] for the target model's phases
+        const float tw_re = kTw.re[c], tw_im = kTw.im[c];
+        __syncthreads();
+
+        for (int it = 0; it < iters; ++it) {
+            // objective (Eq. 16) as IEEE bit patterns: all values are >= +0,
+            // so unsigned order equals float order
+            uint32_t ob[16];
+            uint32_t mx = 0;
+#pragma unroll
+            for (int s = 0; s < 16; ++s) {
+                const float e = fmaf(xr[s], xr[s], xi[s] * xi[s]);
+                ob[s] = __float_as_uint(e * wf[s]);
+                mx = umax(mx, ob[s]);
+            }
+            mx = wave_max_u32(mx);
+            // first (slot, lane) holding the maximum = smallest bin index
+            int idx = 0;
+            float pr = 0.0f, pim = 0.0f;
+#pragma unroll
+            for (int s = 0; s < 16; ++s) {
+                const uint64_t hit = ballot(ob[s] == mx);
+                if (hit) {
+                    const int ln = (int)__builtin_ctzll(hit);
+                    idx = 64 * s + ln;
+                    pr = readlane_f(xr[s], ln);
+                    pim = readlane_f(xi[s], ln);
+                    break;
+                }
+            }
+            const int u = idx >> 5, v = idx & 31;
+            const float cr = gi * pr, ci = gi * pim;    // gamma * p (Eqs. 10-11)
+            if (jb.log != nullptr && lane == 0) jb.log[it] = (uint16_t)idx;
+
+            // model: g += gamma p exp(+j 2 pi (u m + v n) / S) on the target
+            const int q = (u * tm + v * tn) & 31;
+            const float er = __shfl(tw_re, q), ei = __shfl(tw_im, q);
+            acc = fmaf(cr, er, acc);
+            acc = fmaf(ci, ei, acc);
+
+            // residual: R_w[k,l] -= gamma p W[(k-u) mod S, (l-v) mod S]
+            const int base = ((h - u) & 31) * kS + ((c - v) & 31);
+            const float2* wrow = wtab + base;
+#pragma unroll
+            for (int s = 0; s < 16; ++s) {
+                const float2 w = wrow[64 * s];
+                xr[s] = fmaf(-cr, w.x, xr[s]);
+                xr[s] = fmaf(ci, w.y, xr[s]);
+                xi[s] = fmaf(-cr, w.y, xi[s]);
+                xi[s] = fmaf(-ci, w.x, xi[s]);
+            }
+        }
+        __syncthreads();   // the LDS is reused by the next block of a persistent wave
+    } else if (jb.log != nullptr) {
+        for (int it = lane; it < iters; it += 64) jb.log[it] = (uint16_t)0xFFFF;
+    }
+
+    // ---- compose (Sec. II): known pixels copied, unknown pixels Re g
+    if (lane < B * B) {
+        const int y = jb.by * B + ti, xx = jb.bx * B + tj;
+        if (y < jb.height && xx < jb.width) {
+            const int64_t off = (int64_t)y * jb.stride + xx;
+            const uint8_t k = jb.mask[off];
+            jb.out[off] = k ? jb.image[off] : acc;
+        }
+    }
+}
+
+}  // namespace fsr

@@ -1,0 +1,43 @@
+// fsr_internal.h -- declarations shared by the host runtime and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fsr {
+
+constexpr int kS = 32;            // support edge handled by these kernels
+constexpr int kBins = kS * kS;    // 1024 frequency bins per block
+
+// Device tables for one (S = 32, rho) pair: the spatial weight rho^dist
+// (Eq. 5 before masking) and the frequency weight w_f (Eq. 9), both S x S,
+// row-major, float32.
+struct BlockTables {
+    const float* rho_pow;   // [m * 32 + n]
+    const float* freq_w;    // [k * 32 + l]
+};
+
+// One image of a reconstruction call.
+struct ImageDesc {
+    const float* image;
+    const uint8_t* mask;
+    float* out;
+    uint16_t* argmax_log;   // nullable: n_blocks x iterations
+    int32_t height, width;
+    int64_t stride;
+    int32_t iterations;
+    int32_t nbx;            // blocks per row, ceil(width / B)
+    int64_t block_begin;    // first global block id of this image (batched path)
+};
+
+struct PlainLaunch {
+    ImageDesc img;
+    int32_t block, border;  // B, L with B + 2L = 32
+    float gamma;
+    BlockTables tab;
+    int64_t n_blocks;
+};
+
+hipError_t launch_plain(const PlainLaunch& p, hipStream_t stream);
+
+}  // namespace fsr

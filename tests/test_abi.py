@@ -1,0 +1,78 @@
+"""The C ABI: exported symbols and host-side validation (no GPU needed)."""
+import ctypes
+
+import pytest
+
+import paper_2202_13926_amd as fsr
+from paper_2202_13926_amd import binding
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return fsr.load_library()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = fsr.declared_functions()
+    assert "fsr_reconstruct" in names and "fsr_context_create" in names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_status_strings(lib):
+    for code in range(8):
+        assert lib.fsr_status_string(code).decode().startswith("FSR_")
+
+
+def test_defaults_and_block_count(lib):
+    p = fsr.fsr_params_default()
+    assert (p.block, p.border, p.iterations, p.dft, p.flags) == (4, 14, 100, 0, 0)
+    assert abs(p.rho - 0.7) < 1e-7 and p.gamma == 0.5
+    assert fsr.fsr_num_blocks(1080, 1920, 4) == 129600
+    assert fsr.fsr_num_blocks(37, 50, 4) == 10 * 13
+    assert fsr.fsr_num_blocks(0, 5, 4) == -1
+
+
+@pytest.mark.parametrize("kw", [
+    dict(block=0), dict(border=-1), dict(block=3), dict(block=4, border=15),
+    dict(iterations=-1), dict(rho=0.0), dict(rho=1.5), dict(gamma=0.0), dict(gamma=1.01),
+    dict(rho=float("nan")), dict(dft=7), dict(flags=1),
+])
+def test_invalid_params_rejected(lib, kw):
+    with pytest.raises(fsr.FsrError) as e:
+        fsr.fsr_params_validate(fsr.make_params(**kw))
+    assert e.value.status == binding.FSR_ERR_INVALID_ARG
+    assert lib.fsr_last_error_message().decode()
+
+
+def test_valid_params_accepted():
+    for kw in (dict(), dict(block=2, border=15), dict(block=8, border=12, iterations=0),
+               dict(rho=1.0, gamma=1.0), dict(block=4, border=6)):
+        fsr.fsr_params_validate(fsr.make_params(**kw))
+
+
+def _call(lib, ctx, image, mask, out, H, W, stride, params, log=None):
+    return lib.fsr_reconstruct(ctx, image, mask, out, H, W, stride, ctypes.byref(params), log, None)
+
+
+def test_reconstruct_validates_before_touching_the_device(lib):
+    p = fsr.make_params()
+    fake_ctx = ctypes.c_void_p(0x1000)        # never dereferenced: validation fails first
+    img, msk, out = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x20000000), ctypes.c_void_p(0x40000000)
+    assert _call(lib, None, img, msk, out, 8, 8, 8, p) == binding.FSR_ERR_INVALID_ARG
+    assert _call(lib, fake_ctx, None, msk, out, 8, 8, 8, p) == binding.FSR_ERR_INVALID_ARG
+    assert _call(lib, fake_ctx, img, msk, out, 0, 8, 8, p) == binding.FSR_ERR_INVALID_ARG
+    assert _call(lib, fake_ctx, img, msk, out, 8, 8, 7, p) == binding.FSR_ERR_INVALID_ARG
+    # out overlapping image
+    assert _call(lib, fake_ctx, img, msk, ctypes.c_void_p(0x10000 + 64), 8, 8, 8, p) == binding.FSR_ERR_INVALID_ARG
+    # out overlapping mask
+    assert _call(lib, fake_ctx, img, msk, ctypes.c_void_p(0x20000000 + 8), 8, 8, 8, p) == binding.FSR_ERR_INVALID_ARG
+    # valid but outside this build: support 16
+    p16 = fsr.make_params(block=4, border=6)
+    assert _call(lib, fake_ctx, img, msk, out, 8, 8, 8, p16) == binding.FSR_ERR_UNSUPPORTED
+    assert _call(lib, fake_ctx, img, msk, out, 8, 8, 8, fsr.make_params(block=12, border=10)) == binding.FSR_ERR_UNSUPPORTED
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    with pytest.raises(fsr.FsrError):
+        binding.load_library(str(tmp_path / "nope.so"))
