@@ -29,6 +29,11 @@
  *     the weighted least-squares coefficient and Eq. 12 holds exactly.
  *   - Argmax ties: larger objective wins; equal objectives go to the smaller
  *     linear index k*S + l (tie_larger = 1 flips this, for tests only).
+ *   - Precision of the argmax decision (`decision`): 0 compares the FP64
+ *     objectives; 1 takes the decision at the GPU kernel's precision: each
+ *     objective is rounded to float32 and its 4 lowest mantissa bits are
+ *     cleared before comparing (ties again to the smaller index).  Only the
+ *     comparison changes; every other step stays in FP64.
  *   - The twiddle table is exactly conjugate-symmetric so that the spectra of
  *     real inputs are bitwise Hermitian.
  *   - A support with no known pixel (W[0,0] == 0) runs no iteration; its
@@ -48,6 +53,20 @@
 #endif
 
 #define FSRO_API __attribute__((visibility("default")))
+
+/* Objective used for comparisons: the value itself (decision 0), or its
+ * float32 rounding with the 4 lowest mantissa bits cleared (decision 1),
+ * returned as a double so both compare with the same operators. */
+static double decision_value(double obj, int decision)
+{
+    if (decision == 0) return obj;
+    float f = (float)obj;
+    uint32_t u;
+    memcpy(&u, &f, sizeof u);
+    u &= ~(uint32_t)0xF;
+    memcpy(&f, &u, sizeof f);
+    return (double)f;
+}
 
 /* t[q] = exp(-j 2 pi q / S), q in [0, S), with t[S-q] = conj(t[q]) exactly
  * and the quarter points set exactly when S is a multiple of 4. */
@@ -148,7 +167,7 @@ FSRO_API void fsro_dft2_real(int S, const double *x, double *Xr, double *Xi)
  * Returns 1 when the support holds no known pixel (no iteration ran), else 0.
  */
 FSRO_API int fsro_block(int S, int iters, double rho, double gamma, int tie_larger,
-                        const double *ft, const uint8_t *known,
+                        int decision, const double *ft, const uint8_t *known,
                         double *Gr_out, double *Gi_out, double *Rr_out, double *Ri_out,
                         uint16_t *log_idx, double *log_p)
 {
@@ -177,7 +196,7 @@ FSRO_API int fsro_block(int S, int iters, double rho, double gamma, int tie_larg
         int best = 0;
         double best_obj = -1.0;
         for (int b = 0; b < n2; ++b) {
-            double obj = wf[b] * (Rr[b] * Rr[b] + Ri[b] * Ri[b]);
+            double obj = decision_value(wf[b] * (Rr[b] * Rr[b] + Ri[b] * Ri[b]), decision);
             if (tie_larger ? (obj >= best_obj) : (obj > best_obj)) {
                 best_obj = obj;
                 best = b;
@@ -244,7 +263,7 @@ static void gather_support(const double *img, const uint8_t *mask, int H, int W,
  * (row-major B x B; entries of out-of-image pixels are left untouched). */
 static int reconstruct_one(const double *img, const uint8_t *mask, int H, int W, long stride,
                            int B, int L, int iters, double rho, double gamma, int tie_larger,
-                           long block_id, double *out_target, uint16_t *log_idx, double *log_p)
+                           int decision, long block_id, double *out_target, uint16_t *log_idx, double *log_p)
 {
     const int S = B + 2 * L, n2 = S * S;
     const int nbx = (W + B - 1) / B;
@@ -253,8 +272,8 @@ static int reconstruct_one(const double *img, const uint8_t *mask, int H, int W,
     uint8_t *known = malloc(n2);
     double *Gr = malloc(sizeof(double) * n2), *Gi = malloc(sizeof(double) * n2);
     gather_support(img, mask, H, W, stride, B, L, by, bx, ft, known);
-    int empty = fsro_block(S, iters, rho, gamma, tie_larger, ft, known, Gr, Gi, NULL, NULL,
-                           log_idx, log_p);
+    int empty = fsro_block(S, iters, rho, gamma, tie_larger, decision, ft, known, Gr, Gi,
+                           NULL, NULL, log_idx, log_p);
     for (int i = 0; i < B; ++i)
         for (int j = 0; j < B; ++j) {
             int m = L + i, n = L + j;
@@ -277,7 +296,7 @@ static int reconstruct_one(const double *img, const uint8_t *mask, int H, int W,
  */
 FSRO_API long fsro_reconstruct(const double *img, const uint8_t *mask, double *out,
                                int H, int W, long stride, int B, int L, int iters,
-                               double rho, double gamma, int tie_larger,
+                               double rho, double gamma, int tie_larger, int decision,
                                uint16_t *log_idx, int threads)
 {
     const int nby = (H + B - 1) / B, nbx = (W + B - 1) / B;
@@ -291,7 +310,8 @@ FSRO_API long fsro_reconstruct(const double *img, const uint8_t *mask, double *o
         double tgt[32 * 32];
         double *t = (B * B <= 32 * 32) ? tgt : malloc(sizeof(double) * B * B);
         empty += reconstruct_one(img, mask, H, W, stride, B, L, iters, rho, gamma, tie_larger,
-                                 b, t, log_idx ? log_idx + b * (long)iters : NULL, NULL);
+                                 decision, b, t, log_idx ? log_idx + b * (long)iters : NULL,
+                                 NULL);
         const int by = (int)(b / nbx), bx = (int)(b % nbx);
         for (int i = 0; i < B; ++i)
             for (int j = 0; j < B; ++j) {
@@ -314,7 +334,7 @@ FSRO_API long fsro_reconstruct(const double *img, const uint8_t *mask, double *o
  */
 FSRO_API long fsro_reconstruct_blocks(const double *img, const uint8_t *mask,
                                       int H, int W, long stride, int B, int L, int iters,
-                                      double rho, double gamma, int tie_larger,
+                                      double rho, double gamma, int tie_larger, int decision,
                                       const int64_t *block_ids, long n, double *out_targets,
                                       uint16_t *log_idx, double *log_p, int threads)
 {
@@ -327,7 +347,7 @@ FSRO_API long fsro_reconstruct_blocks(const double *img, const uint8_t *mask,
         double *t = out_targets + i * (long)B * B;
         for (int q = 0; q < B * B; ++q) t[q] = NAN;
         empty += reconstruct_one(img, mask, H, W, stride, B, L, iters, rho, gamma, tie_larger,
-                                 (long)block_ids[i], t,
+                                 decision, (long)block_ids[i], t,
                                  log_idx ? log_idx + i * (long)iters : NULL,
                                  log_p ? log_p + 2 * i * (long)iters : NULL);
     }

@@ -165,31 +165,24 @@ __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int
         __syncthreads();
 
         for (int it = 0; it < iters; ++it) {
-            // objective (Eq. 16) as IEEE bit patterns: all values are >= +0,
-            // so unsigned order equals float order
-            uint32_t ob[16];
-            uint32_t mx = 0;
+            // objective (Eq. 16) as an argmax key: the IEEE bits of the
+            // non-negative float32 objective (so unsigned order is float
+            // order) with the 4 lowest mantissa bits replaced by 15 - slot.
+            // Objectives that agree to 2^-19 relative tie, and ties go to the
+            // smaller slot, then (below) to the lower lane: the smaller bin.
+            uint32_t lmax = 0;
 #pragma unroll
             for (int s = 0; s < 16; ++s) {
                 const float e = fmaf(xr[s], xr[s], xi[s] * xi[s]);
-                ob[s] = __float_as_uint(e * wf[s]);
-                mx = umax(mx, ob[s]);
+                const uint32_t key = (__float_as_uint(e * wf[s]) & 0xFFFFFFF0u) | (uint32_t)(15 - s);
+                lmax = umax(lmax, key);
             }
-            mx = wave_max_u32(mx);
-            // first (slot, lane) holding the maximum = smallest bin index
-            int idx = 0;
-            float pr = 0.0f, pim = 0.0f;
-#pragma unroll
-            for (int s = 0; s < 16; ++s) {
-                const uint64_t hit = ballot(ob[s] == mx);
-                if (hit) {
-                    const int ln = (int)__builtin_ctzll(hit);
-                    idx = 64 * s + ln;
-                    pr = readlane_f(xr[s], ln);
-                    pim = readlane_f(xi[s], ln);
-                    break;
-                }
-            }
+            const uint32_t mx = wave_max_u32(lmax);
+            const int ln = (int)__builtin_ctzll(ballot(lmax == mx));
+            const int slot = 15 - (int)(mx & 15u);
+            const int idx = 64 * slot + ln;
+            const float pr = readlane_f(xr[slot], ln);
+            const float pim = readlane_f(xi[slot], ln);
             const int u = idx >> 5, v = idx & 31;
             const float cr = gi * pr, ci = gi * pim;    // gamma * p (Eqs. 10-11)
             if (jb.log != nullptr && lane == 0) jb.log[it] = (uint16_t)idx;

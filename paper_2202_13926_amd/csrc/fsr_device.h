@@ -159,9 +159,12 @@ __device__ __forceinline__ void dft32_lane_pair(float (&re)[16], float (&im)[16]
 }
 
 // ---------------------------------------------------------------- wave reductions
+// DPP move whose masked-out lanes read 0, the identity of the unsigned max
+// (objective bit patterns are never negative), so the move can fuse into the
+// max instruction.
 template <int kCtrl, int kRowMask = 0xf>
 __device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, kCtrl, kRowMask, 0xf, false);
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kCtrl, kRowMask, 0xf, false);
 }
 
 __device__ __forceinline__ uint32_t umax(uint32_t a, uint32_t b) { return a > b ? a : b; }

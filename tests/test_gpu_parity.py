@@ -7,7 +7,10 @@ Acceptance on every case (floating point path, FP32 on the GPU):
   * PSNR gap <= 0.05 dB;
   * the bin chosen at each logged (block, iteration) agrees with the oracle's
     on at least 99 % of them.
-Both sides receive the same float32 image (the oracle in float64).
+Both sides receive the same float32 image (the oracle in float64), and the
+oracle takes its argmax decisions at the kernel's precision (float32
+objective, 4 low mantissa bits dropped, ties to the smaller bin); all its
+other arithmetic is FP64.
 """
 import numpy as np
 import pytest
@@ -25,6 +28,7 @@ TOL_CODE = 1.0
 FRAC = 0.999
 PSNR_GAP = 0.05
 ARGMAX = 0.99
+KERNEL = oracle.DECISION_KERNEL
 
 
 @pytest.fixture(scope="module")
@@ -95,7 +99,8 @@ def test_small64_exhaustive(ctx):
     img, mask = w.inputs()
     img32 = img.astype(np.float32)
     g, gl = run_gpu(ctx, img32, mask, params_of(w))
-    o, ol, n_empty = oracle.reconstruct(img32.astype(np.float64), mask, w.iterations, log=True)
+    o, ol, n_empty = oracle.reconstruct(img32.astype(np.float64), mask, w.iterations, log=True,
+                                        decision=KERNEL)
     assert n_empty == 0
     rep = parity_report(img32, mask, g, o, gl, ol)
     assert_parity(rep, "small64")
@@ -125,7 +130,7 @@ def test_full_size_frames_sampled(ctx, name, k):
     nbx = -(-w.width // w.block)
     ids = _sampled_ids(w.n_blocks, nbx, 7, k)
     ot, ol, _, _ = oracle.reconstruct_blocks(img32.astype(np.float64), mask, ids, w.iterations,
-                                             log=True)
+                                             log=True, decision=KERNEL)
     gt = block_targets(g, ids, w.block)
     ref = block_targets(img32, ids, w.block)
     mt = block_targets(mask.astype(np.float64), ids, w.block)
@@ -148,7 +153,8 @@ def _exhaustive(ctx, img, mask, params, stride=None, name=""):
     g, gl = run_gpu(ctx, img32, mask, params, stride=stride)
     o, ol, n_empty = oracle.reconstruct(img32.astype(np.float64), mask, params.iterations,
                                         block_size=params.block, border=params.border,
-                                        rho=params.rho, gamma=params.gamma, log=True)
+                                        rho=params.rho, gamma=params.gamma, log=True,
+                                        decision=KERNEL)
     rep = parity_report(img32, mask, g, o, gl if params.iterations else None,
                         ol if params.iterations else None)
     assert_parity(rep, name)
@@ -220,7 +226,7 @@ def test_parameter_variants(ctx, rho, gamma, iters):
     img32 = img.astype(np.float32)
     g, gl = run_gpu(ctx, img32, mask, params)
     o, ol, _ = oracle.reconstruct(img32.astype(np.float64), mask, iters, rho=rho, gamma=gamma,
-                                  log=True)
+                                  log=True, decision=KERNEL)
     rep = parity_report(img32, mask, g, o, gl, ol)
     print(f"[parity] variant rho{rho} gamma{gamma} I{iters}: {rep}", flush=True)
     assert rep["known_bitwise"] and rep["psnr_gap"] <= PSNR_GAP
