@@ -36,6 +36,36 @@ def algorithmic_flops_per_block(S: int, B: int, iters: int) -> float:
     return 12.0 * S * S * iters + 5.0 * S * S * math.log2(S * S) + 4.0 * B * B * iters
 
 
+KERNEL_SOURCES = ("paper_2202_13926_amd/csrc/fsr_block.h", "paper_2202_13926_amd/csrc/fsr_device.h",
+                  "paper_2202_13926_amd/csrc/fsr_plain.hip", "paper_2202_13926_amd/csrc/fsr_internal.h")
+PMC_SUMMARY = "profiles/fsr_plain_s32_fhd_quarter_pmc.md"
+
+
+def kernel_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE summary,
+    or None when the kernel sources changed after the counters were taken."""
+    try:
+        text = open(os.path.join(ROOT, PMC_SUMMARY)).read()
+    except OSError:
+        return None
+    for line in text.splitlines():
+        if line.startswith("traffic-record:"):
+            kv = dict(item.split("=") for item in line.split()[1:])
+            if kv.get("kernel_hash") != kernel_hash():
+                return None
+            return int(kv["fetch_bytes"]) + int(kv["write_bytes"])
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -44,7 +74,23 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-blocks", type=int, default=32000,
                     help="blocks in the oracle's timed sample")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 5 device-to-device copies of MIB MiB (a kernel of known "
+                         "traffic, used to scale the FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
+
+
+def copy_calibration(mib: int):
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": n * 4, "copy_calibration_bytes_written": n * 4,
+                      "copies": 5}), flush=True)
 
 
 def cpu_baseline(img32, mask, w, n_blocks_sample):
@@ -65,6 +111,9 @@ def cpu_baseline(img32, mask, w, n_blocks_sample):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                                    "(multi-GPU sharding is described in the design notes only)"}))
@@ -141,7 +190,7 @@ def main():
                      "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
                      "algorithmic_flop_per_launch": flops,
                      "avg_launch_ms": round(ms_per_step, 5),
-                     "traffic": None},
+                     "traffic": measured_traffic()},
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(img32, mask, w, args.cpu_blocks)

@@ -161,7 +161,11 @@ __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int
 #pragma unroll
         for (int s = 0; s < 16; ++s) wf[s] = tab.freq_w[(2 * s + h) * kS + c];
         // lane i of tw_re/tw_im holds t32[i & 31] for the target model's phases
-        const float tw_re = kTw.re[c], tw_im = kTw.im[c];
+        const int tw_re = __float_as_int(kTw.re[c]), tw_im = __float_as_int(kTw.im[c]);
+        // loop-invariant lane offsets: bpermute byte addresses of the target
+        // phases are 4 q, LDS byte offsets of W are 256 row + 8 column
+        const int tm4 = opaque(4 * tm), tn4 = opaque(4 * tn);
+        const int h256 = opaque(256 * h), c8 = opaque(8 * c);
         __syncthreads();
 
         for (int it = 0; it < iters; ++it) {
@@ -188,14 +192,17 @@ __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int
             if (jb.log != nullptr && lane == 0) jb.log[it] = (uint16_t)idx;
 
             // model: g += gamma p exp(+j 2 pi (u m + v n) / S) on the target
-            const int q = (u * tm + v * tn) & 31;
-            const float er = __shfl(tw_re, q), ei = __shfl(tw_im, q);
+            const int q4 = mad_u24(v, tn4, mul_u24(u, tm4)) & 124;
+            const float er = __int_as_float(__builtin_amdgcn_ds_bpermute(q4, tw_re));
+            const float ei = __int_as_float(__builtin_amdgcn_ds_bpermute(q4, tw_im));
             acc = fmaf(cr, er, acc);
             acc = fmaf(ci, ei, acc);
 
-            // residual: R_w[k,l] -= gamma p W[(k-u) mod S, (l-v) mod S]
-            const int base = ((h - u) & 31) * kS + ((c - v) & 31);
-            const float2* wrow = wtab + base;
+            // residual: R_w[k,l] -= gamma p W[(k-u) mod S, (l-v) mod S]; slot s
+            // reads duplicated row (h - u) mod 32 + 2s at byte offset 512 s
+            const int woff = ((h256 - 256 * u) & 0x1F00) | ((c8 - 8 * v) & 0xF8);
+            const float2* wrow = reinterpret_cast<const float2*>(
+                reinterpret_cast<const char*>(wtab) + woff);
 #pragma unroll
             for (int s = 0; s < 16; ++s) {
                 const float2 w = wrow[64 * s];

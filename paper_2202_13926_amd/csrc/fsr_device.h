@@ -197,6 +197,29 @@ __device__ __forceinline__ float wave_sum_f32(float v) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
+// Returns x unchanged but hides how it was computed from the optimiser, so a
+// precomputed lane constant (e.g. 8 * lane) is used as is instead of being
+// re-derived inside a loop.
+__device__ __forceinline__ int opaque(int x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+// a * b + c on the 24-bit multiplier (full rate), a wave-uniform.  The
+// compiler otherwise widens small products to the quarter-rate 32/64-bit
+// multiply-add.
+__device__ __forceinline__ int mad_u24(int a, int b, int c) {
+    int r;
+    asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "s"(a), "v"(b), "v"(c));
+    return r;
+}
+
+__device__ __forceinline__ int mul_u24(int a, int b) {
+    int r;
+    asm("v_mul_u32_u24 %0, %1, %2" : "=v"(r) : "s"(a), "v"(b));
+    return r;
+}
+
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 __device__ __forceinline__ float readlane_f(float v, int lane) {
