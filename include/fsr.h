@@ -127,6 +127,80 @@ FSR_API fsr_status fsr_reconstruct(fsr_context *ctx, const float *image, const u
                            float *out, int32_t height, int32_t width, int64_t stride,
                            const fsr_params *params, uint16_t *argmax_log, void *stream);
 
+/* ------------------------------------------------------------------ batches */
+
+/* One image of a batch.  Pointers are device memory owned by the caller; the
+ * meaning of each field is that of the same argument of fsr_reconstruct. */
+typedef struct fsr_image_desc {
+    const float *image;
+    const uint8_t *mask;
+    float *out;
+    uint16_t *argmax_log;   /* NULL, or fsr_num_blocks(...) x iterations   */
+    int32_t height, width;
+    int64_t stride;
+    int32_t iterations;     /* this image's I (params->iterations ignored)  */
+    int32_t reserved;       /* must be 0                                    */
+} fsr_image_desc;
+
+/* How the batched kernel distributes blocks over the GPU. */
+typedef struct fsr_batch_schedule {
+    int32_t waves_per_group;  /* wavefronts per workgroup: 1, 2 or 4          */
+    int32_t chunk;            /* 0: one wavefront per block on a plain grid;
+                                 1..64: persistent wavefronts take `chunk`
+                                 consecutive blocks per pop of a global queue */
+    int32_t groups_per_cu;    /* persistent grid = compute units x this (1..16);
+                                 ignored when chunk == 0                       */
+    int32_t reserved;         /* must be 0                                     */
+} fsr_batch_schedule;
+
+/* Device workspace needed for a batch of n_images images (queue head and
+ * the device copy of the descriptors).  The caller allocates it. */
+FSR_API fsr_status fsr_batched_workspace_size(int32_t n_images, size_t *bytes);
+
+/*
+ * Reconstructs n_images images of any sizes and iteration counts in one
+ * kernel launch (plus a one-thread queue reset when the schedule uses the
+ * queue).  The blocks of all images form one index space ordered by
+ * decreasing iteration count, so the heaviest blocks start first.  Every
+ * block runs the same arithmetic as in fsr_reconstruct: each image's output
+ * and log are bitwise identical to a fsr_reconstruct call on it alone.
+ *   descs      HOST array of n_images descriptors (copied; may be reused
+ *              once the call returns)
+ *   params     block, border, rho, gamma, dft shared by all images
+ *   schedule   NULL: the schedule fsr_batch_autotune chose for a batch of
+ *              this size class on this context, else a plain grid
+ *   workspace  device memory of >= fsr_batched_workspace_size bytes; it must
+ *              not be in use by another call that has not completed
+ * Asynchronous on `stream`; must not be called while `stream` is being
+ * captured (use fsr_batch_graph_create for graphs).
+ */
+FSR_API fsr_status fsr_reconstruct_batched(fsr_context *ctx, const fsr_image_desc *descs,
+                                           int32_t n_images, const fsr_params *params,
+                                           const fsr_batch_schedule *schedule, void *workspace,
+                                           size_t workspace_bytes, void *stream);
+
+/* Times the batch under a fixed list of candidate schedules (each run
+ * reconstructs the batch, so outputs are written), stores the fastest on the
+ * context for this batch's size class and returns it in *best.  Blocks the
+ * host until the timing runs finish. */
+FSR_API fsr_status fsr_batch_autotune(fsr_context *ctx, const fsr_image_desc *descs,
+                                      int32_t n_images, const fsr_params *params,
+                                      void *workspace, size_t workspace_bytes, void *stream,
+                                      fsr_batch_schedule *best);
+
+/* A batch captured once into a HIP graph (queue reset + batched kernel) and
+ * replayed many times: the images' device buffers are fixed at creation and
+ * their contents are read at each replay.  Creation uploads the descriptors
+ * synchronously.  The context, the workspace and every buffer must outlive
+ * the graph; replays of one graph must not overlap. */
+typedef struct fsr_batch_graph fsr_batch_graph;
+FSR_API fsr_status fsr_batch_graph_create(fsr_context *ctx, const fsr_image_desc *descs,
+                                          int32_t n_images, const fsr_params *params,
+                                          const fsr_batch_schedule *schedule, void *workspace,
+                                          size_t workspace_bytes, fsr_batch_graph **out);
+FSR_API fsr_status fsr_batch_graph_launch(fsr_batch_graph *graph, void *stream);
+FSR_API fsr_status fsr_batch_graph_destroy(fsr_batch_graph *graph);
+
 #ifdef __cplusplus
 }
 #endif

@@ -40,6 +40,25 @@ class fsr_params(ctypes.Structure):
                 ("gamma", ctypes.c_float), ("dft", ctypes.c_int32), ("flags", ctypes.c_uint32)]
 
 
+class fsr_image_desc(ctypes.Structure):
+    _fields_ = [("image", ctypes.c_void_p), ("mask", ctypes.c_void_p), ("out", ctypes.c_void_p),
+                ("argmax_log", ctypes.c_void_p), ("height", ctypes.c_int32),
+                ("width", ctypes.c_int32), ("stride", ctypes.c_int64),
+                ("iterations", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class fsr_batch_schedule(ctypes.Structure):
+    _fields_ = [("waves_per_group", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("groups_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (self.waves_per_group, self.chunk, self.groups_per_cu)
+
+
+def make_schedule(waves_per_group=1, chunk=0, groups_per_cu=10) -> fsr_batch_schedule:
+    return fsr_batch_schedule(waves_per_group, chunk, groups_per_cu, 0)
+
+
 def make_params(block=4, border=14, iterations=100, rho=0.7, gamma=0.5, dft=FSR_DFT_FP32,
                 flags=0) -> fsr_params:
     return fsr_params(block, border, iterations, rho, gamma, dft, flags)
@@ -76,6 +95,18 @@ def load_library(path: str | None = None):
         "fsr_context_create": (ctypes.c_int, [ctypes.POINTER(vp), i32]),
         "fsr_context_destroy": (ctypes.c_int, [vp]),
         "fsr_reconstruct": (ctypes.c_int, [vp, vp, vp, vp, i32, i32, i64, P, vp, vp]),
+        "fsr_batched_workspace_size": (ctypes.c_int, [i32, ctypes.POINTER(ctypes.c_size_t)]),
+        "fsr_reconstruct_batched": (ctypes.c_int, [vp, ctypes.POINTER(fsr_image_desc), i32, P,
+                                                   ctypes.POINTER(fsr_batch_schedule), vp,
+                                                   ctypes.c_size_t, vp]),
+        "fsr_batch_autotune": (ctypes.c_int, [vp, ctypes.POINTER(fsr_image_desc), i32, P, vp,
+                                              ctypes.c_size_t, vp,
+                                              ctypes.POINTER(fsr_batch_schedule)]),
+        "fsr_batch_graph_create": (ctypes.c_int, [vp, ctypes.POINTER(fsr_image_desc), i32, P,
+                                                  ctypes.POINTER(fsr_batch_schedule), vp,
+                                                  ctypes.c_size_t, ctypes.POINTER(vp)]),
+        "fsr_batch_graph_launch": (ctypes.c_int, [vp, vp]),
+        "fsr_batch_graph_destroy": (ctypes.c_int, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -177,10 +208,12 @@ def _image_args(image, mask, out):
         raise FsrError(FSR_ERR_INVALID_ARG, "image, mask and out must be device tensors")
     if not (image.device == mask.device == out.device):
         raise FsrError(FSR_ERR_INVALID_ARG, "image, mask and out must be on one device")
-    strides = {t.stride() for t in (image, mask, out)}
-    if len(strides) != 1 or image.stride(1) != 1:
+    H, W = image.shape
+    # strides of size-1 dimensions carry no meaning in torch; normalise them
+    rows = {t.stride(0) if H > 1 else W for t in (image, mask, out)}
+    if len(rows) != 1 or any(W > 1 and t.stride(1) != 1 for t in (image, mask, out)):
         raise FsrError(FSR_ERR_INVALID_ARG, "image, mask and out need unit column stride and one row stride")
-    return image.shape[0], image.shape[1], image.stride(0)
+    return H, W, rows.pop()
 
 
 def fsr_reconstruct(ctx: Context, image, mask, out, params: fsr_params, argmax_log=None,
@@ -217,3 +250,98 @@ def reconstruct(image, mask, params: fsr_params | None = None, ctx: Context | No
     if log:
         return out, lg[:, :params.iterations]
     return out
+
+
+# ---------------------------------------------------------------- batches
+class BatchItem:
+    """One image of a batch: device tensors plus its iteration count."""
+
+    def __init__(self, image, mask, out, iterations: int, argmax_log=None):
+        self.image, self.mask, self.out = image, mask, out
+        self.iterations = int(iterations)
+        self.argmax_log = argmax_log
+
+
+def _descs(items, block):
+    arr = (fsr_image_desc * max(len(items), 1))()
+    for i, it in enumerate(items):
+        H, W, stride = _image_args(it.image, it.mask, it.out)
+        log_ptr = None
+        if it.argmax_log is not None:
+            n = fsr_num_blocks(H, W, block)
+            if (not it.argmax_log.is_cuda or not it.argmax_log.is_contiguous()
+                    or it.argmax_log.element_size() != 2 or it.argmax_log.numel() < n * it.iterations):
+                raise FsrError(FSR_ERR_INVALID_ARG, f"image {i}: argmax_log must be a contiguous "
+                                                    "16-bit device tensor of N*I entries")
+            log_ptr = it.argmax_log.data_ptr()
+        arr[i] = fsr_image_desc(it.image.data_ptr(), it.mask.data_ptr(), it.out.data_ptr(), log_ptr,
+                                H, W, stride, it.iterations, 0)
+    return arr
+
+
+def fsr_batched_workspace_size(n_images: int) -> int:
+    b = ctypes.c_size_t()
+    _check(load_library().fsr_batched_workspace_size(int(n_images), ctypes.byref(b)))
+    return int(b.value)
+
+
+class Workspace:
+    """Device workspace of a batch, owned by a torch tensor."""
+
+    def __init__(self, n_images: int, device):
+        import torch
+        self.nbytes = fsr_batched_workspace_size(n_images)
+        self.tensor = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
+
+    @property
+    def ptr(self):
+        return ctypes.c_void_p(self.tensor.data_ptr())
+
+
+def fsr_reconstruct_batched(ctx: Context, items, params: fsr_params, workspace: Workspace,
+                            schedule: fsr_batch_schedule | None = None, stream=None) -> None:
+    descs = _descs(items, params.block)
+    dev = items[0].image.device if items else None
+    sched = ctypes.byref(schedule) if schedule is not None else None
+    _check(load_library().fsr_reconstruct_batched(
+        ctx.handle, descs, len(items), ctypes.byref(params), sched, workspace.ptr,
+        workspace.nbytes, _stream_handle(stream, dev) if dev is not None else None))
+
+
+def fsr_batch_autotune(ctx: Context, items, params: fsr_params, workspace: Workspace,
+                       stream=None) -> fsr_batch_schedule:
+    descs = _descs(items, params.block)
+    best = fsr_batch_schedule()
+    _check(load_library().fsr_batch_autotune(
+        ctx.handle, descs, len(items), ctypes.byref(params), workspace.ptr, workspace.nbytes,
+        _stream_handle(stream, items[0].image.device), ctypes.byref(best)))
+    return best
+
+
+class BatchGraph:
+    """A batch captured into a HIP graph (see fsr_batch_graph_create)."""
+
+    def __init__(self, ctx: Context, items, params: fsr_params, workspace: Workspace,
+                 schedule: fsr_batch_schedule | None = None):
+        descs = _descs(items, params.block)
+        self._ptr = ctypes.c_void_p()
+        sched = ctypes.byref(schedule) if schedule is not None else None
+        _check(load_library().fsr_batch_graph_create(
+            ctx.handle, descs, len(items), ctypes.byref(params), sched, workspace.ptr,
+            workspace.nbytes, ctypes.byref(self._ptr)))
+        self._keep = (ctx, items, workspace)     # buffers must outlive the graph
+        self.device = items[0].image.device if items else None
+
+    def launch(self, stream=None):
+        _check(load_library().fsr_batch_graph_launch(self._ptr, _stream_handle(stream, self.device)))
+
+    def close(self):
+        if self._ptr:
+            load_library().fsr_batch_graph_destroy(self._ptr)
+            self._ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

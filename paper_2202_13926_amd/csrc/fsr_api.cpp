@@ -37,6 +37,16 @@ fsr_status fail(fsr_status st, const char* fmt, ...) {
 
 namespace fsr {
 
+fsr_status errorf(fsr_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
 fsr_status set_error(fsr_status st, const char* msg) {
     g_last_error = msg;
     return st;

@@ -1,8 +1,364 @@
-// fsr_batched.cpp -- host side of the batched path (persistent kernel).
+// fsr_batched.cpp -- host side of the batched path: planning (validation,
+// queue order, prefix sums), descriptor upload, schedules, the autotuner and
+// HIP-graph capture.
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
 #include "fsr_runtime.h"
 
 namespace fsr {
 
-void release_batch_state(BatchState& st) { st.reserved = nullptr; }
+namespace {
+
+constexpr size_t kCtrlBytes = 256;                 // queue head, padded
+constexpr int64_t kMaxBlocks = int64_t(1) << 30;   // keeps the 32-bit queue head from wrapping
+
+size_t workspace_bytes_for(int32_t n) {
+    return kCtrlBytes + ((size_t)n * sizeof(DevDesc) + 255) / 256 * 256;
+}
+
+struct BatchPlan {
+    std::vector<DevDesc> table;   // queue order
+    int64_t total_blocks = 0;
+    double work = 0.0;            // sum over images of blocks x iterations
+    int32_t max_iterations = 0;
+};
+
+fsr_status check_schedule(const fsr_batch_schedule* s) {
+    if (!s) return FSR_OK;
+    if (s->waves_per_group != 1 && s->waves_per_group != 2 && s->waves_per_group != 4)
+        return errorf(FSR_ERR_INVALID_ARG, "waves_per_group must be 1, 2 or 4 (got %d)", s->waves_per_group);
+    if (s->chunk < 0 || s->chunk > 64)
+        return errorf(FSR_ERR_INVALID_ARG, "chunk must lie in [0, 64] (got %d)", s->chunk);
+    if (s->chunk > 0 && (s->groups_per_cu < 1 || s->groups_per_cu > 16))
+        return errorf(FSR_ERR_INVALID_ARG, "groups_per_cu must lie in [1, 16] (got %d)", s->groups_per_cu);
+    if (s->reserved != 0) return errorf(FSR_ERR_INVALID_ARG, "schedule.reserved must be 0");
+    return FSR_OK;
+}
+
+fsr_status plan_batch(const fsr_image_desc* descs, int32_t n, const fsr_params* params,
+                      BatchPlan* plan) {
+    if (n < 0) return errorf(FSR_ERR_INVALID_ARG, "n_images must be >= 0 (got %d)", n);
+    if (n > 0 && !descs) return errorf(FSR_ERR_INVALID_ARG, "descs is NULL");
+    const int B = params->block;
+    std::vector<int64_t> blocks(n);
+    for (int32_t i = 0; i < n; ++i) {
+        const fsr_image_desc& d = descs[i];
+        fsr_status st = validate_image(d.image, d.mask, d.out, d.height, d.width, d.stride, B);
+        if (st != FSR_OK) return errorf(st, "image %d: %s", i, fsr_last_error_message());
+        if (d.iterations < 0) return errorf(FSR_ERR_INVALID_ARG, "image %d: iterations must be >= 0", i);
+        if (d.reserved != 0) return errorf(FSR_ERR_INVALID_ARG, "image %d: reserved must be 0", i);
+        blocks[i] = fsr_num_blocks(d.height, d.width, B);
+    }
+    // queue order: decreasing iterations, then decreasing size, then input order
+    std::vector<int32_t> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        if (descs[a].iterations != descs[b].iterations) return descs[a].iterations > descs[b].iterations;
+        return blocks[a] > blocks[b];
+    });
+    plan->table.resize(n);
+    int64_t begin = 0;
+    for (int32_t j = 0; j < n; ++j) {
+        const fsr_image_desc& d = descs[order[j]];
+        DevDesc& e = plan->table[j];
+        e.image = d.image;
+        e.mask = d.mask;
+        e.out = d.out;
+        e.argmax_log = d.argmax_log;
+        e.stride = d.stride;
+        e.block_begin = begin;
+        e.height = d.height;
+        e.width = d.width;
+        e.iterations = d.iterations;
+        e.nbx = (d.width + B - 1) / B;
+        begin += blocks[order[j]];
+        plan->work += (double)blocks[order[j]] * (double)(d.iterations + 8);
+        plan->max_iterations = std::max(plan->max_iterations, d.iterations);
+    }
+    if (begin > kMaxBlocks) return errorf(FSR_ERR_UNSUPPORTED, "a batch may hold at most 2^30 blocks");
+    plan->total_blocks = begin;
+    return FSR_OK;
+}
+
+// Size class of a batch: log2 of its work and its largest iteration count.
+uint64_t size_class(const BatchPlan& plan) {
+    uint64_t w = 0;
+    for (double x = plan.work; x >= 2.0; x /= 2.0) ++w;
+    return (w << 32) | (uint64_t)(uint32_t)plan.max_iterations;
+}
+
+fsr_batch_schedule default_schedule() { return fsr_batch_schedule{1, 0, 10, 0}; }
+
+fsr_status cu_count(fsr_context* ctx, int* out) {
+    BatchState& bs = context_batch(ctx);
+    if (bs.cu_count == 0) {
+        hipDeviceProp_t prop;
+        hipError_t e = hipGetDeviceProperties(&prop, context_device(ctx));
+        if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+        bs.cu_count = prop.multiProcessorCount;
+    }
+    *out = bs.cu_count;
+    return FSR_OK;
+}
+
+struct Prepared {
+    BatchLaunch launch{};
+    fsr_batch_schedule schedule{};
+    int64_t groups = 0;
+};
+
+// Everything common to eager launches, autotuning and graph capture.
+fsr_status prepare(fsr_context* ctx, const fsr_image_desc* descs, int32_t n, const fsr_params* params,
+                   const fsr_batch_schedule* schedule, void* workspace, size_t ws_bytes,
+                   BatchPlan* plan, Prepared* prep) {
+    if (!ctx) return errorf(FSR_ERR_INVALID_ARG, "context is NULL");
+    fsr_status st = validate_params(params);
+    if (st != FSR_OK) return st;
+    if ((st = check_supported(params)) != FSR_OK) return st;
+    if (params->dft != FSR_DFT_FP32)
+        return errorf(FSR_ERR_UNSUPPORTED, "this build's batched path runs the FP32 DFT");
+    if ((st = check_schedule(schedule)) != FSR_OK) return st;
+    if ((st = plan_batch(descs, n, params, plan)) != FSR_OK) return st;
+    if (!workspace && n > 0) return errorf(FSR_ERR_INVALID_ARG, "workspace is NULL");
+    if (ws_bytes < workspace_bytes_for(n))
+        return errorf(FSR_ERR_INVALID_ARG, "workspace of %zu bytes is smaller than the %zu needed",
+                      ws_bytes, workspace_bytes_for(n));
+    prep->launch.descs = reinterpret_cast<const DevDesc*>(static_cast<char*>(workspace) + kCtrlBytes);
+    prep->launch.counter = static_cast<unsigned*>(workspace);
+    prep->launch.total_blocks = plan->total_blocks;
+    prep->launch.n_images = n;
+    prep->launch.block = params->block;
+    prep->launch.border = params->border;
+    prep->launch.gamma = params->gamma;
+    if (schedule) {
+        prep->schedule = *schedule;
+    } else {
+        BatchState& bs = context_batch(ctx);
+        std::lock_guard<std::mutex> lock(context_mutex(ctx));
+        auto it = bs.tuned.find(size_class(*plan));
+        prep->schedule = it != bs.tuned.end() ? it->second : default_schedule();
+    }
+    prep->launch.chunk = prep->schedule.chunk;
+    if (prep->schedule.chunk > 0) {
+        int cus = 0;
+        if ((st = cu_count(ctx, &cus)) != FSR_OK) return st;
+        prep->groups = (int64_t)cus * prep->schedule.groups_per_cu;
+    }
+    return FSR_OK;
+}
+
+// Copies the descriptor table into the workspace, ordered on `stream`,
+// through the context's pinned staging buffer.
+fsr_status upload_async(fsr_context* ctx, const BatchPlan& plan, void* workspace, hipStream_t stream) {
+    const size_t bytes = plan.table.size() * sizeof(DevDesc);
+    if (bytes == 0) return FSR_OK;
+    BatchState& bs = context_batch(ctx);
+    std::lock_guard<std::mutex> lock(context_mutex(ctx));
+    hipError_t e;
+    if (bs.staging_done) {                       // the previous upload must have read the staging
+        if ((e = hipEventSynchronize(bs.staging_done)) != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    } else if ((e = hipEventCreateWithFlags(&bs.staging_done, hipEventDisableTiming)) != hipSuccess) {
+        return hip_fail(e, "hipEventCreate");
+    }
+    if (bs.staging_bytes < bytes) {
+        if (bs.staging) (void)hipHostFree(bs.staging);
+        bs.staging = nullptr;
+        bs.staging_bytes = 0;
+        if ((e = hipHostMalloc(&bs.staging, bytes, hipHostMallocDefault)) != hipSuccess)
+            return errorf(FSR_ERR_OUT_OF_MEMORY, "hipHostMalloc(%zu): %s", bytes, hipGetErrorString(e));
+        bs.staging_bytes = bytes;
+    }
+    std::memcpy(bs.staging, plan.table.data(), bytes);
+    e = hipMemcpyAsync(static_cast<char*>(workspace) + kCtrlBytes, bs.staging, bytes,
+                       hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return hip_fail(e, "descriptor upload");
+    if ((e = hipEventRecord(bs.staging_done, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    return FSR_OK;
+}
+
+fsr_status launch_prepared(const Prepared& prep, hipStream_t stream) {
+    hipError_t e = launch_batched(prep.launch, prep.schedule.waves_per_group, prep.groups, stream);
+    if (e != hipSuccess) return hip_fail(e, "launch of the batched kernel");
+    return FSR_OK;
+}
+
+}  // namespace
+
+void release_batch_state(BatchState& st) {
+    if (st.staging_done) {
+        (void)hipEventSynchronize(st.staging_done);
+        (void)hipEventDestroy(st.staging_done);
+    }
+    if (st.staging) (void)hipHostFree(st.staging);
+    st.staging = nullptr;
+    st.staging_bytes = 0;
+    st.staging_done = nullptr;
+    st.tuned.clear();
+}
 
 }  // namespace fsr
+
+using namespace fsr;
+
+struct fsr_batch_graph {
+    int device = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+fsr_status fsr_batched_workspace_size(int32_t n_images, size_t* bytes) {
+    if (!bytes) return errorf(FSR_ERR_INVALID_ARG, "bytes is NULL");
+    if (n_images < 0) return errorf(FSR_ERR_INVALID_ARG, "n_images must be >= 0 (got %d)", n_images);
+    *bytes = workspace_bytes_for(n_images);
+    return FSR_OK;
+}
+
+fsr_status fsr_reconstruct_batched(fsr_context* ctx, const fsr_image_desc* descs, int32_t n_images,
+                                   const fsr_params* params, const fsr_batch_schedule* schedule,
+                                   void* workspace, size_t workspace_bytes, void* stream) {
+    BatchPlan plan;
+    Prepared prep;
+    fsr_status st = prepare(ctx, descs, n_images, params, schedule, workspace, workspace_bytes, &plan, &prep);
+    if (st != FSR_OK) return st;
+    if (plan.total_blocks == 0) return FSR_OK;
+    DeviceGuard g(context_device(ctx));
+    if (g.error() != hipSuccess) return hip_fail(g.error(), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(s, &cap);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
+    if (cap != hipStreamCaptureStatusNone)
+        return errorf(FSR_ERR_UNSUPPORTED, "stream is being captured: use fsr_batch_graph_create");
+    if ((st = context_tables(ctx, params->rho, &prep.launch.tab)) != FSR_OK) return st;
+    if ((st = upload_async(ctx, plan, workspace, s)) != FSR_OK) return st;
+    return launch_prepared(prep, s);
+}
+
+fsr_status fsr_batch_autotune(fsr_context* ctx, const fsr_image_desc* descs, int32_t n_images,
+                              const fsr_params* params, void* workspace, size_t workspace_bytes,
+                              void* stream, fsr_batch_schedule* best) {
+    if (!best) return errorf(FSR_ERR_INVALID_ARG, "best is NULL");
+    static const fsr_batch_schedule kCandidates[] = {
+        {1, 0, 10, 0}, {2, 0, 5, 0},
+        {1, 1, 10, 0}, {1, 2, 10, 0}, {1, 4, 10, 0}, {1, 8, 10, 0}, {1, 16, 10, 0},
+        {2, 2, 5, 0}, {2, 4, 5, 0}, {2, 8, 5, 0}, {1, 4, 8, 0}, {4, 4, 2, 0},
+    };
+    BatchPlan plan;
+    Prepared prep;
+    fsr_status st = prepare(ctx, descs, n_images, params, &kCandidates[0], workspace, workspace_bytes,
+                            &plan, &prep);
+    if (st != FSR_OK) return st;
+    *best = default_schedule();
+    if (plan.total_blocks == 0) return FSR_OK;
+    DeviceGuard g(context_device(ctx));
+    if (g.error() != hipSuccess) return hip_fail(g.error(), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = context_tables(ctx, params->rho, &prep.launch.tab)) != FSR_OK) return st;
+    if ((st = upload_async(ctx, plan, workspace, s)) != FSR_OK) return st;
+    int cus = 0;
+    if ((st = cu_count(ctx, &cus)) != FSR_OK) return st;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    hipError_t e = hipEventCreate(&t0);
+    if (e == hipSuccess) e = hipEventCreate(&t1);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    float best_ms = -1.0f;
+    for (const fsr_batch_schedule& cand : kCandidates) {
+        Prepared p = prep;
+        p.schedule = cand;
+        p.launch.chunk = cand.chunk;
+        p.groups = cand.chunk > 0 ? (int64_t)cus * cand.groups_per_cu : 0;
+        if ((st = launch_prepared(p, s)) != FSR_OK) break;          // warm-up run
+        if ((e = hipEventRecord(t0, s)) != hipSuccess) { st = hip_fail(e, "hipEventRecord"); break; }
+        for (int r = 0; r < 2 && st == FSR_OK; ++r) st = launch_prepared(p, s);
+        if (st != FSR_OK) break;
+        if ((e = hipEventRecord(t1, s)) != hipSuccess) { st = hip_fail(e, "hipEventRecord"); break; }
+        if ((e = hipEventSynchronize(t1)) != hipSuccess) { st = hip_fail(e, "hipEventSynchronize"); break; }
+        float ms = 0.0f;
+        if ((e = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess) { st = hip_fail(e, "hipEventElapsedTime"); break; }
+        if (best_ms < 0.0f || ms < best_ms) {
+            best_ms = ms;
+            *best = cand;
+        }
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    if (st != FSR_OK) return st;
+    std::lock_guard<std::mutex> lock(context_mutex(ctx));
+    context_batch(ctx).tuned[size_class(plan)] = *best;
+    return FSR_OK;
+}
+
+fsr_status fsr_batch_graph_create(fsr_context* ctx, const fsr_image_desc* descs, int32_t n_images,
+                                  const fsr_params* params, const fsr_batch_schedule* schedule,
+                                  void* workspace, size_t workspace_bytes, fsr_batch_graph** out) {
+    if (!out) return errorf(FSR_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    BatchPlan plan;
+    Prepared prep;
+    fsr_status st = prepare(ctx, descs, n_images, params, schedule, workspace, workspace_bytes, &plan, &prep);
+    if (st != FSR_OK) return st;
+    DeviceGuard g(context_device(ctx));
+    if (g.error() != hipSuccess) return hip_fail(g.error(), "hipSetDevice");
+    if ((st = context_tables(ctx, params->rho, &prep.launch.tab)) != FSR_OK) return st;
+    hipError_t e;
+    if (!plan.table.empty()) {
+        e = hipMemcpy(static_cast<char*>(workspace) + kCtrlBytes, plan.table.data(),
+                      plan.table.size() * sizeof(DevDesc), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "descriptor upload");
+    }
+    hipStream_t cs = nullptr;
+    if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(e, "hipStreamCreate");
+    fsr_batch_graph* gr = new (std::nothrow) fsr_batch_graph();
+    if (!gr) {
+        (void)hipStreamDestroy(cs);
+        return errorf(FSR_ERR_OUT_OF_MEMORY, "graph allocation failed");
+    }
+    gr->device = context_device(ctx);
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        if (plan.total_blocks > 0) st = launch_prepared(prep, cs);
+        hipError_t e2 = hipStreamEndCapture(cs, &gr->graph);
+        if (st == FSR_OK && e2 != hipSuccess) st = hip_fail(e2, "hipStreamEndCapture");
+    } else {
+        st = hip_fail(e, "hipStreamBeginCapture");
+    }
+    if (st == FSR_OK && (e = hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0)) != hipSuccess)
+        st = hip_fail(e, "hipGraphInstantiate");
+    (void)hipStreamDestroy(cs);
+    if (st != FSR_OK) {
+        if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+        if (gr->graph) (void)hipGraphDestroy(gr->graph);
+        delete gr;
+        return st;
+    }
+    *out = gr;
+    return FSR_OK;
+}
+
+fsr_status fsr_batch_graph_launch(fsr_batch_graph* graph, void* stream) {
+    if (!graph || !graph->exec) return errorf(FSR_ERR_INVALID_ARG, "graph is NULL");
+    DeviceGuard g(graph->device);
+    if (g.error() != hipSuccess) return hip_fail(g.error(), "hipSetDevice");
+    hipError_t e = hipGraphLaunch(graph->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return FSR_OK;
+}
+
+fsr_status fsr_batch_graph_destroy(fsr_batch_graph* graph) {
+    if (!graph) return FSR_OK;
+    {
+        DeviceGuard g(graph->device);
+        if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+        if (graph->graph) (void)hipGraphDestroy(graph->graph);
+    }
+    delete graph;
+    return FSR_OK;
+}
+
+}  // extern "C"

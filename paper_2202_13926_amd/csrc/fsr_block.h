@@ -48,21 +48,21 @@ __device__ __forceinline__ void dft2_real_to_bins(float (&xr)[16], float (&xi)[1
         pr[(k + 16 * h) * kPitch + c] = xr[k];
         pi[(k + 16 * h) * kPitch + c] = xi[k];
     }
-    __syncthreads();
+    wave_sync();
     // pass 2: along n for every k = c; slot s takes n = 2s + h
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
         xr[s] = pr[c * kPitch + 2 * s + h];
         xi[s] = pi[c * kPitch + 2 * s + h];
     }
-    __syncthreads();
+    wave_sync();
     dft32_lane_pair(xr, xi, h);                 // slot l' -> (k = c, l = l' + 16h)
 #pragma unroll
     for (int l = 0; l < 16; ++l) {
         pr[c * kPitch + l + 16 * h] = xr[l];
         pi[c * kPitch + l + 16 * h] = xi[l];
     }
-    __syncthreads();
+    wave_sync();
     // bin layout with exact Hermitian symmetrisation: (k, l) = (2s + h, c)
     const int lm = (kS - c) & 31;
 #pragma unroll
@@ -73,7 +73,7 @@ __device__ __forceinline__ void dft2_real_to_bins(float (&xr)[16], float (&xi)[1
         xr[s] = 0.5f * (ar + br);
         xi[s] = 0.5f * (ai - bi);
     }
-    __syncthreads();
+    wave_sync();
 }
 
 // Everything a block needs to know about its image and the method.
@@ -89,8 +89,14 @@ struct BlockJob {
 };
 
 __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int L, float gamma,
-                                                  const BlockTables& tab, float* lds) {
-    const int lane = threadIdx.x & 63;
+                                                  const BlockTables& tab_in, float* lds) {
+    // Per-block values are made opaque so that a caller looping over blocks
+    // (the persistent kernel) does not hoist the table loads and lane
+    // constants out of its loop and keep them live across every block.
+    const int lane = opaque((int)(threadIdx.x & 63));
+    BlockTables tab;
+    tab.rho_pow = opaque_ptr(tab_in.rho_pow);
+    tab.freq_w = opaque_ptr(tab_in.freq_w);
     const int c = lane & 31, h = lane >> 5;
     const int y0 = jb.by * B - L, x0 = jb.bx * B - L;
 
@@ -166,7 +172,7 @@ __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int
         // phases are 4 q, LDS byte offsets of W are 256 row + 8 column
         const int tm4 = opaque(4 * tm), tn4 = opaque(4 * tn);
         const int h256 = opaque(256 * h), c8 = opaque(8 * c);
-        __syncthreads();
+        wave_sync();
 
         for (int it = 0; it < iters; ++it) {
             // objective (Eq. 16) as an argmax key: the IEEE bits of the
@@ -212,7 +218,7 @@ __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int
                 xi[s] = fmaf(-ci, w.x, xi[s]);
             }
         }
-        __syncthreads();   // the LDS is reused by the next block of a persistent wave
+        wave_sync();   // the LDS is reused by the next block of a persistent wave
     } else if (jb.log != nullptr) {
         for (int it = lane; it < iters; it += 64) jb.log[it] = (uint16_t)0xFFFF;
     }

@@ -220,6 +220,21 @@ __device__ __forceinline__ int mul_u24(int a, int b) {
     return r;
 }
 
+// Orders this wavefront's LDS accesses (its own LDS region only): a fence at
+// wavefront scope plus a code-motion barrier.  Workgroup barriers are never
+// used by the block routine, so workgroups may hold several wavefronts that
+// work on different blocks with different control flow.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <typename T>
+__device__ __forceinline__ T* opaque_ptr(T* p) {
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 __device__ __forceinline__ float readlane_f(float v, int lane) {

@@ -40,4 +40,36 @@ struct PlainLaunch {
 
 hipError_t launch_plain(const PlainLaunch& p, hipStream_t stream);
 
+// Device-side descriptor of one image of a batch (64 bytes).  Images are
+// stored in queue order; block_begin is the prefix sum of block counts.
+struct DevDesc {
+    const float* image;
+    const uint8_t* mask;
+    float* out;
+    uint16_t* argmax_log;
+    int64_t stride;
+    int64_t block_begin;
+    int32_t height, width;
+    int32_t iterations;
+    int32_t nbx;
+};
+static_assert(sizeof(DevDesc) == 64, "descriptor layout");
+
+struct BatchLaunch {
+    const DevDesc* descs;   // device, n_images entries
+    unsigned* counter;      // device queue head (reset before every launch)
+    int64_t total_blocks;
+    int32_t n_images;
+    int32_t chunk;          // blocks per queue pop; 0 = one wavefront per block, no queue
+    int32_t block, border;
+    float gamma;
+    BlockTables tab;
+};
+
+// Launches the queue reset (when chunk > 0) and the batched kernel with
+// `waves_per_group` wavefronts per workgroup and `groups` workgroups
+// (persistent mode) on `stream`.
+hipError_t launch_batched(const BatchLaunch& p, int waves_per_group, int64_t groups,
+                          hipStream_t stream);
+
 }  // namespace fsr

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
 #include <mutex>
 
 #include "fsr.h"
@@ -27,15 +28,21 @@ private:
     hipError_t err_ = hipSuccess;
 };
 
-// Per-context state of the batched path (tuning results and reusable
-// device buffers).  Filled in by fsr_batched.cpp.
+// Per-context state of the batched path: pinned staging for descriptor
+// uploads, the event that marks the last upload as consumed, the device's
+// compute-unit count and the schedules chosen by the autotuner.
 struct BatchState {
-    void* reserved = nullptr;
+    void* staging = nullptr;
+    size_t staging_bytes = 0;
+    hipEvent_t staging_done = nullptr;
+    int cu_count = 0;
+    std::map<uint64_t, fsr_batch_schedule> tuned;
 };
 
 void release_batch_state(BatchState& st);
 
 fsr_status set_error(fsr_status st, const char* msg);
+fsr_status errorf(fsr_status st, const char* fmt, ...);
 fsr_status hip_fail(hipError_t e, const char* what);
 fsr_status validate_params(const fsr_params* p);
 fsr_status check_supported(const fsr_params* p);

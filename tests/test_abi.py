@@ -76,3 +76,46 @@ def test_reconstruct_validates_before_touching_the_device(lib):
 def test_missing_library_fails_loudly(tmp_path):
     with pytest.raises(fsr.FsrError):
         binding.load_library(str(tmp_path / "nope.so"))
+
+
+def test_batched_workspace_size(lib):
+    assert fsr.fsr_batched_workspace_size(0) == 256
+    assert fsr.fsr_batched_workspace_size(1) == 512
+    assert fsr.fsr_batched_workspace_size(64) == 256 + 64 * 64
+    with pytest.raises(fsr.FsrError):
+        fsr.fsr_batched_workspace_size(-1)
+
+
+def test_batched_validates_before_touching_the_device(lib):
+    p = fsr.make_params()
+    ctx = ctypes.c_void_p(0x1000)            # never dereferenced: validation fails first
+    good = binding.fsr_image_desc(0x10000, 0x20000000, 0x40000000, None, 8, 8, 8, 10, 0)
+
+    def call(descs, n, ws=0x50000000, ws_bytes=1 << 20, sched=None, params=p):
+        arr = (binding.fsr_image_desc * max(n, 1))(*descs) if descs is not None else None
+        return lib.fsr_reconstruct_batched(ctx, arr, n, ctypes.byref(params),
+                                           ctypes.byref(sched) if sched else None,
+                                           ws, ws_bytes, None)
+
+    E = binding.FSR_ERR_INVALID_ARG
+    assert call([good], -1) == E
+    assert call(None, 2) == E
+    bad = binding.fsr_image_desc(0x10000, 0x20000000, 0x40000000, None, 8, 8, 8, 10, 1)
+    assert call([good, bad], 2) == E                                   # reserved != 0
+    neg = binding.fsr_image_desc(0x10000, 0x20000000, 0x40000000, None, 8, 8, 8, -1, 0)
+    assert call([neg], 1) == E                                         # iterations < 0
+    alias = binding.fsr_image_desc(0x10000, 0x20000000, 0x10000 + 4, None, 8, 8, 8, 10, 0)
+    assert call([alias], 1) == E                                       # out overlaps image
+    assert call([good], 1, ws_bytes=100) == E                          # workspace too small
+    assert call([good], 1, ws=None) == E
+    for s in (fsr.make_schedule(3, 0, 10), fsr.make_schedule(1, 65, 10), fsr.make_schedule(1, 4, 0),
+              binding.fsr_batch_schedule(1, 0, 10, 7)):
+        assert call([good], 1, sched=s) == E
+    assert call([good], 1, params=fsr.make_params(block=4, border=6)) == binding.FSR_ERR_UNSUPPORTED
+    assert lib.fsr_last_error_message().decode()
+    out = ctypes.c_void_p()
+    arr = (binding.fsr_image_desc * 1)(good)
+    assert lib.fsr_batch_graph_create(ctx, arr, 1, ctypes.byref(p), None, None, 1 << 20,
+                                      ctypes.byref(out)) == E
+    assert lib.fsr_batch_graph_launch(None, None) == E
+    assert lib.fsr_batch_graph_destroy(None) == binding.FSR_OK

@@ -1,0 +1,197 @@
+"""Batched path (persistent kernel, queue, graphs, autotuner) on the GPU.
+
+Every block of a batch runs the same arithmetic as the one-image kernel, so
+each image's output and argmax log must be bitwise identical to a
+fsr_reconstruct call on it alone, whatever the schedule, the batch
+composition or the replay.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth.metrics import parity_report
+
+torch = pytest.importorskip("torch")
+import paper_2202_13926_amd as fsr  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+SCHEDULES = [fsr.make_schedule(1, 0, 10), fsr.make_schedule(2, 0, 5), fsr.make_schedule(4, 0, 2),
+             fsr.make_schedule(1, 1, 10), fsr.make_schedule(1, 4, 10), fsr.make_schedule(2, 8, 5),
+             fsr.make_schedule(4, 64, 2), fsr.make_schedule(1, 3, 1)]
+
+
+def announce(name):
+    print(f"\n[gpu case] {name}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return fsr.Context(0)
+
+
+def uneven_batch(seed=5):
+    shapes = [(64, 64, "quarter", 100), (37, 50, "uniform:0.3", 25), (96, 128, "quarter", 200),
+              (128, 96, "uniform:0.5", 50), (1, 1, "quarter", 10), (33, 1, "uniform:0.2", 0),
+              (150, 200, "macroblock", 100), (8, 8, "quarter", 60)]
+    items = []
+    for i, (h, w, mk, it) in enumerate(shapes):
+        img = synth.make_image(h, w, seed * 100 + i)
+        mask = synth.make_mask(mk, h, w, seed * 100 + i + 50)
+        items.append((img.astype(np.float32), mask, it))
+    return items
+
+
+def to_items(batch, with_log=True):
+    items = []
+    for img, mask, it in batch:
+        ti = torch.from_numpy(img).to(DEV)
+        tm = torch.from_numpy(mask).to(DEV)
+        out = torch.full_like(ti, -1.0)
+        n = fsr.fsr_num_blocks(img.shape[0], img.shape[1], 4)
+        lg = torch.full((n, max(it, 1)), -1, dtype=torch.int16, device=DEV) if with_log else None
+        items.append(fsr.BatchItem(ti, tm, out, it, lg))
+    return items
+
+
+def plain_reference(ctx, batch):
+    refs = []
+    for img, mask, it in batch:
+        p = fsr.make_params(iterations=it)
+        ti, tm = torch.from_numpy(img).to(DEV), torch.from_numpy(mask).to(DEV)
+        out, lg = fsr.reconstruct(ti, tm, p, ctx=ctx, log=True)
+        torch.cuda.synchronize()
+        refs.append((out.cpu().numpy(), lg.cpu().numpy()))
+    return refs
+
+
+def results(items):
+    torch.cuda.synchronize()
+    return [(it.out.cpu().numpy(), it.argmax_log.cpu().numpy()[:, :it.iterations]) for it in items]
+
+
+def assert_same(got, refs):
+    for k, ((g, gl), (r, rl)) in enumerate(zip(got, refs)):
+        assert np.array_equal(g, r), f"image {k} output differs"
+        assert np.array_equal(gl, rl), f"image {k} argmax log differs"
+
+
+def test_batched_matches_single_image_calls(ctx):
+    announce("uneven batch under every schedule vs one-image calls")
+    batch = uneven_batch()
+    refs = plain_reference(ctx, batch)
+    ws = fsr.Workspace(len(batch), DEV)
+    for sched in SCHEDULES:
+        items = to_items(batch)
+        fsr.fsr_reconstruct_batched(ctx, items, fsr.make_params(), ws, sched)
+        assert_same(results(items), refs)
+
+
+def test_batch_composition_does_not_matter(ctx):
+    announce("same images in another order, in a subset and twice")
+    batch = uneven_batch()
+    refs = plain_reference(ctx, batch)
+    ws = fsr.Workspace(2 * len(batch), DEV)
+    order = [3, 0, 7, 2, 6, 1, 5, 4]
+    items = to_items([batch[i] for i in order])
+    fsr.fsr_reconstruct_batched(ctx, items, fsr.make_params(), ws, fsr.make_schedule(1, 2, 10))
+    assert_same(results(items), [refs[i] for i in order])
+    items = to_items(batch[2:5] + batch[2:5])
+    fsr.fsr_reconstruct_batched(ctx, items, fsr.make_params(), ws, fsr.make_schedule(2, 4, 5))
+    assert_same(results(items), refs[2:5] + refs[2:5])
+
+
+def test_batched_against_oracle(ctx):
+    announce("uneven batch vs the FP64 oracle")
+    batch = uneven_batch(7)
+    items = to_items(batch)
+    ws = fsr.Workspace(len(batch), DEV)
+    fsr.fsr_reconstruct_batched(ctx, items, fsr.make_params(), ws, fsr.make_schedule(1, 4, 10))
+    got = results(items)
+    for (img, mask, it), (g, gl) in zip(batch, got):
+        o, ol, _ = oracle.reconstruct(img.astype(np.float64), mask, it, log=True,
+                                      decision=oracle.DECISION_KERNEL)
+        rep = parity_report(img, mask, g, o, gl if it else None, ol if it else None)
+        print(f"[parity] batch image {img.shape} I={it}: {rep}", flush=True)
+        assert rep["known_bitwise"] and rep["frac_le_1"] >= 0.999 and rep["psnr_gap"] <= 0.05
+        if it:
+            assert rep["argmax_agree"] >= 0.99
+
+
+def test_graph_replays_match_eager(ctx):
+    announce("graph capture: replays vs eager, inputs updated in place")
+    batch = uneven_batch(9)
+    ws = fsr.Workspace(len(batch), DEV)
+    eager = to_items(batch)
+    fsr.fsr_reconstruct_batched(ctx, eager, fsr.make_params(), ws, fsr.make_schedule(1, 4, 10))
+    ref = results(eager)
+    items = to_items(batch)
+    ws2 = fsr.Workspace(len(batch), DEV)
+    g = fsr.BatchGraph(ctx, items, fsr.make_params(), ws2, fsr.make_schedule(1, 4, 10))
+    for rep in range(3):
+        for it in items:
+            it.out.fill_(-5.0)
+            it.argmax_log.fill_(-3)
+        torch.cuda.synchronize()
+        g.launch()
+        got = results(items)
+        assert_same(got, ref)
+        # unrelated eager work between replays
+        fsr.fsr_reconstruct_batched(ctx, eager, fsr.make_params(), ws, fsr.make_schedule(2, 0, 5))
+        torch.cuda.synchronize()
+    # new frame contents in the same buffers
+    flipped = [(img[::-1, ::-1].copy(), mask[::-1, ::-1].copy(), it)
+               for img, mask, it in batch]
+    for it, (img, mask, _) in zip(items, flipped):
+        it.image.copy_(torch.from_numpy(img))
+        it.mask.copy_(torch.from_numpy(mask))
+    torch.cuda.synchronize()
+    g.launch()
+    assert_same(results(items), plain_reference(ctx, flipped))
+    g.close()
+
+
+def test_autotune_picks_a_valid_schedule(ctx):
+    announce("autotuner")
+    batch = uneven_batch(11)
+    refs = plain_reference(ctx, batch)
+    ws = fsr.Workspace(len(batch), DEV)
+    items = to_items(batch)
+    best = fsr.fsr_batch_autotune(ctx, items, fsr.make_params(), ws)
+    print("[autotune] best", best.as_tuple(), flush=True)
+    assert best.waves_per_group in (1, 2, 4) and 0 <= best.chunk <= 64
+    assert_same(results(items), refs)
+    items = to_items(batch)
+    fsr.fsr_reconstruct_batched(ctx, items, fsr.make_params(), ws)   # uses the tuned schedule
+    assert_same(results(items), refs)
+
+
+def test_synthetic_uneven_batch_sampled(ctx):
+    announce("64 uneven images (256x256 .. 1920x1080, I in {50,100,200}), sampled vs oracle")
+    specs = synth.batch_items(64)
+    ws = fsr.Workspace(len(specs), DEV)
+    batch, items = [], []
+    for s in specs:
+        img, mask = s.inputs()
+        img = img.astype(np.float32)
+        batch.append((img, mask, s.iterations))
+    items = to_items(batch)
+    fsr.fsr_reconstruct_batched(ctx, items, fsr.make_params(), ws, fsr.make_schedule(1, 4, 10))
+    got = results(items)
+    rng = np.random.default_rng(3)
+    for k in rng.choice(len(batch), 6, replace=False):
+        img, mask, it = batch[k]
+        n = fsr.fsr_num_blocks(img.shape[0], img.shape[1], 4)
+        ids = np.sort(rng.choice(n, size=min(300, n), replace=False))
+        ot, ol, _, _ = oracle.reconstruct_blocks(img.astype(np.float64), mask, ids, it, log=True,
+                                                 decision=oracle.DECISION_KERNEL)
+        g, gl = got[k]
+        nbx = -(-img.shape[1] // 4)
+        gt = np.stack([g[b // nbx * 4:b // nbx * 4 + 4, b % nbx * 4:b % nbx * 4 + 4] for b in ids])
+        rt = np.stack([img[b // nbx * 4:b // nbx * 4 + 4, b % nbx * 4:b % nbx * 4 + 4] for b in ids])
+        mt = np.stack([mask[b // nbx * 4:b // nbx * 4 + 4, b % nbx * 4:b % nbx * 4 + 4] for b in ids])
+        rep = parity_report(rt, mt, gt, ot, gl[ids], ol)
+        print(f"[parity] synthetic batch image {k} {img.shape} I={it}: {rep}", flush=True)
+        assert rep["known_bitwise"] and rep["frac_le_1"] >= 0.999 and rep["argmax_agree"] >= 0.99
