@@ -74,6 +74,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-blocks", type=int, default=32000,
                     help="blocks in the oracle's timed sample")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 64-image batched comparison")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (a kernel of known "
                          "traffic, used to scale the FETCH_SIZE / WRITE_SIZE counters)")
@@ -107,6 +109,66 @@ def cpu_baseline(img32, mask, w, n_blocks_sample):
     return {"value": px / dt / 1e6, "unit": "Mpixel/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(ids)} seeded random blocks ({px} pixels) of the same frame, "
                       f"FP64 C oracle, OpenMP over blocks, {dt:.2f} s wall"}
+
+
+def bench_batched(ctx, steps: int = 5):
+    """64 uneven images (256x256 .. 1920x1080, quarter or 10-50 % uniform loss,
+    I in {50, 100, 200}): the tuned batched launch, its graph replay and the
+    plain loop of one fsr_reconstruct launch per image, on the same buffers."""
+    import torch
+
+    import paper_2202_13926_amd as fsr
+    import synth
+
+    dev = torch.device("cuda:0")
+    specs = synth.batch_items(64)
+    items, pixels, work = [], 0, 0
+    for sp in specs:
+        img, mask = sp.inputs()
+        ti = torch.from_numpy(img.astype(np.float32)).to(dev)
+        tm = torch.from_numpy(mask).to(dev)
+        items.append(fsr.BatchItem(ti, tm, torch.empty_like(ti), sp.iterations))
+        pixels += img.size
+        work += fsr.fsr_num_blocks(sp.height, sp.width, 4) * sp.iterations
+    params = fsr.make_params()
+    ws = fsr.Workspace(len(items), dev)
+    stream = torch.cuda.current_stream(dev)
+    t0 = time.perf_counter()
+    best = fsr.fsr_batch_autotune(ctx, items, params, ws, stream)
+    tune_s = time.perf_counter() - t0
+
+    def timed(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(n):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    batched_ms = timed(lambda: fsr.fsr_reconstruct_batched(ctx, items, params, ws, best, stream), steps)
+    graph = fsr.BatchGraph(ctx, items, params, fsr.Workspace(len(items), dev), best)
+    graph_ms = timed(lambda: graph.launch(stream), steps)
+    graph.close()
+
+    def plain_loop():
+        for it in items:
+            p = fsr.make_params(iterations=it.iterations)
+            fsr.fsr_reconstruct(ctx, it.image, it.mask, it.out, p, None, stream)
+
+    plain_ms = timed(plain_loop, max(2, steps // 2))
+    mpx = pixels / 1e6
+    return {"workload": "64 uneven images 256x256..1920x1080, quarter or 10-50% uniform loss, "
+                        "I in {50,100,200}, S=32, rho=0.7, gamma=0.5",
+            "pixels": pixels, "block_iterations": int(work),
+            "schedule": {"waves_per_group": best.waves_per_group, "chunk": best.chunk,
+                         "groups_per_cu": best.groups_per_cu}, "autotune_s": round(tune_s, 3),
+            "batched_ms": round(batched_ms, 3), "batched_mpx_s": round(mpx / batched_ms * 1e3, 2),
+            "graph_ms": round(graph_ms, 3), "graph_mpx_s": round(mpx / graph_ms * 1e3, 2),
+            "plain_loop_ms": round(plain_ms, 3), "plain_loop_mpx_s": round(mpx / plain_ms * 1e3, 2),
+            "speedup_vs_plain_loop": round(plain_ms / min(batched_ms, graph_ms), 3)}
 
 
 def main():
@@ -192,6 +254,8 @@ def main():
                      "avg_launch_ms": round(ms_per_step, 5),
                      "traffic": measured_traffic()},
     }
+    if not args.no_batched:
+        res["batched"] = bench_batched(ctx)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(img32, mask, w, args.cpu_blocks)
     ctx.close()

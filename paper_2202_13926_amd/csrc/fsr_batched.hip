@@ -13,15 +13,24 @@ __global__ void fsr_queue_reset(unsigned* counter) {
     if (threadIdx.x == 0) *counter = 0u;
 }
 
-__device__ __forceinline__ void batch_block(const BatchLaunch& p, int64_t g, float* lds) {
-    // last image whose first block is <= g (descriptors sorted by block_begin)
+// Image of global block g: the cached one when g still lies in [begin, end),
+// else a binary search over the descriptors (sorted by block_begin).
+__device__ __forceinline__ void locate(const BatchLaunch& p, int64_t g, int& img, int64_t& begin,
+                                       int64_t& end) {
+    if (g >= begin && g < end) return;
     int lo = 0, hi = p.n_images - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (p.descs[mid].block_begin <= g) lo = mid;
         else hi = mid - 1;
     }
-    const DevDesc& d = p.descs[lo];
+    img = lo;
+    begin = p.descs[lo].block_begin;
+    end = lo + 1 < p.n_images ? p.descs[lo + 1].block_begin : p.total_blocks;
+}
+
+__device__ __forceinline__ void batch_block(const BatchLaunch& p, int64_t g, int img, float* lds) {
+    const DevDesc& d = p.descs[img];
     const int64_t local = g - d.block_begin;
     BlockJob jb;
     jb.image = d.image;
@@ -40,12 +49,16 @@ __device__ __forceinline__ void batch_block(const BatchLaunch& p, int64_t g, flo
 template <int kWaves>
 __global__ __launch_bounds__(64 * kWaves) void fsr_batched_s32(BatchLaunch p) {
     __shared__ float lds[kWaves * kLdsFloats];
-    const int wave = threadIdx.x >> 6;
+    // wave-uniform by construction; readfirstlane lets the compiler see it,
+    // so block indices and descriptors stay in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     float* mine = lds + wave * kLdsFloats;
     // [next, end): blocks this wavefront still owns.  Without a queue a
     // wavefront owns exactly one block; with one it refills from the queue.
     int64_t next = 0, end = 0;
+    int img = 0;
+    int64_t img_begin = 0, img_end = 0;   // empty: the first block searches
     if (p.chunk <= 0) {
         const int64_t groups = (p.total_blocks + kWaves - 1) / kWaves;
         next = xcd_contiguous(blockIdx.x, groups) * kWaves + wave;
@@ -62,7 +75,8 @@ __global__ __launch_bounds__(64 * kWaves) void fsr_batched_s32(BatchLaunch p) {
             end = next + p.chunk;
             if (end > p.total_blocks) end = p.total_blocks;
         }
-        batch_block(p, next, mine);
+        locate(p, next, img, img_begin, img_end);
+        batch_block(p, next, img, mine);
         ++next;
     }
 }

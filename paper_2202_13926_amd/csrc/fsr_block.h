@@ -18,7 +18,8 @@
 // rows duplicated (64 rows x 32 bins x float2) so that the rows a lane needs
 // for its 16 bins, (k - u) mod 32 for k = 2s + h, form one contiguous run and
 // every slot's address is the lane's base plus an immediate offset.  The
-// same buffer first serves as the transpose scratch of the DFTs.
+// same buffer first serves as the transpose scratch of the DFTs (lower half)
+// and as the parking place of the first spectrum (upper half).
 #pragma once
 
 #include "fsr_device.h"
@@ -28,12 +29,21 @@ namespace fsr {
 
 constexpr int kLdsFloats = 2 * 64 * kS;   // 4096 floats = 16 KiB
 
-// Transpose scratch: two planes (re, im) of 32 rows x kPitch floats.
+// Transpose scratch: two planes (re, im) of 32 x 32 floats in the lower
+// 8 KiB.  Element (r, j) lives at r * 32 + (j ^ r): rows and columns both
+// map to 32 distinct banks, so row-wise and column-wise accesses of a
+// half-wavefront are conflict-free.  The upper 8 KiB can hold one spectrum
+// in bin layout (see park()).
 __device__ __forceinline__ float* plane_re(float* lds) { return lds; }
-__device__ __forceinline__ float* plane_im(float* lds) { return lds + kS * kPitch; }
+__device__ __forceinline__ float* plane_im(float* lds) { return lds + kS * kS; }
+__device__ __forceinline__ int pidx(int r, int j) { return r * kS + (j ^ r); }
+__device__ __forceinline__ float2* park(float* lds) {
+    return reinterpret_cast<float2*>(lds + 2 * kS * kS);
+}
 
 // 2D DFT of the real tile v (spatial layout) into the bin layout, exactly
-// Hermitian.  Leaves (re, im) of bins 64*s + lane in (xr, xi).
+// Hermitian.  Leaves (re, im) of bins 64*s + lane in (xr, xi).  Uses the
+// lower 8 KiB of the block's LDS only.
 __device__ __forceinline__ void dft2_real_to_bins(float (&xr)[16], float (&xi)[16], float* lds,
                                                   int lane) {
     const int c = lane & 31, h = lane >> 5;
@@ -45,22 +55,22 @@ __device__ __forceinline__ void dft2_real_to_bins(float (&xr)[16], float (&xi)[1
     dft32_lane_pair(xr, xi, h);                 // slot k' -> bin row k = k' + 16h, column n = c
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-        pr[(k + 16 * h) * kPitch + c] = xr[k];
-        pi[(k + 16 * h) * kPitch + c] = xi[k];
+        pr[pidx(k + 16 * h, c)] = xr[k];
+        pi[pidx(k + 16 * h, c)] = xi[k];
     }
     wave_sync();
     // pass 2: along n for every k = c; slot s takes n = 2s + h
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
-        xr[s] = pr[c * kPitch + 2 * s + h];
-        xi[s] = pi[c * kPitch + 2 * s + h];
+        xr[s] = pr[pidx(c, 2 * s + h)];
+        xi[s] = pi[pidx(c, 2 * s + h)];
     }
     wave_sync();
     dft32_lane_pair(xr, xi, h);                 // slot l' -> (k = c, l = l' + 16h)
 #pragma unroll
     for (int l = 0; l < 16; ++l) {
-        pr[c * kPitch + l + 16 * h] = xr[l];
-        pi[c * kPitch + l + 16 * h] = xi[l];
+        pr[pidx(c, l + 16 * h)] = xr[l];
+        pi[pidx(c, l + 16 * h)] = xi[l];
     }
     wave_sync();
     // bin layout with exact Hermitian symmetrisation: (k, l) = (2s + h, c)
@@ -68,8 +78,8 @@ __device__ __forceinline__ void dft2_real_to_bins(float (&xr)[16], float (&xi)[1
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
         const int k = 2 * s + h, km = (kS - k) & 31;
-        const float ar = pr[k * kPitch + c], ai = pi[k * kPitch + c];
-        const float br = pr[km * kPitch + lm], bi = pi[km * kPitch + lm];
+        const float ar = pr[pidx(k, c)], ai = pi[pidx(k, c)];
+        const float br = pr[pidx(km, lm)], bi = pi[pidx(km, lm)];
         xr[s] = 0.5f * (ar + br);
         xi[s] = 0.5f * (ai - bi);
     }
@@ -148,7 +158,20 @@ __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int
         for (int s = 0; s < 16; ++s) xr[s] = (xr[s] - mu) * wr[s];
         float xi[16], wi[16];
         dft2_real_to_bins(xr, xi, lds, lane);
+        // park the first spectrum in the upper half of the LDS while the
+        // second is transformed, so both never occupy registers at once
+        float2* pk = park(lds);
+#pragma unroll
+        for (int s = 0; s < 16; ++s) pk[64 * s + lane] = make_float2(xr[s], xi[s]);
+        wave_sync();
         dft2_real_to_bins(wr, wi, lds, lane);
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const float2 v = pk[64 * s + lane];
+            xr[s] = v.x;
+            xi[s] = v.y;
+        }
+        wave_sync();
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
             xr[s] = fmaf(mu, wr[s], xr[s]);

@@ -18,7 +18,6 @@
 namespace fsr {
 
 constexpr int kSlots = 16;        // bins (or pixels) per lane
-constexpr int kPitch = 33;        // LDS row pitch (floats) of the transpose planes
 
 // ---------------------------------------------------------------- twiddles
 // t[q] = exp(-j 2 pi q / 32).  Built at compile time from the first octant
