@@ -76,6 +76,9 @@ def parse():
                     help="blocks in the oracle's timed sample")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 64-image batched comparison")
+    ap.add_argument("--serve-requests", type=int, default=2400,
+                    help="requests of the served comparison (0 skips it); the stated workload "
+                         "is 10,000 (about 42 s per mode)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (a kernel of known "
                          "traffic, used to scale the FETCH_SIZE / WRITE_SIZE counters)")
@@ -171,6 +174,86 @@ def bench_batched(ctx, steps: int = 5):
             "speedup_vs_plain_loop": round(plain_ms / min(batched_ms, graph_ms), 3)}
 
 
+def bench_served(ctx, n_requests: int, rate_hz: float = 240.0, budget: int = 4 << 30):
+    """Poisson stream of frames (720p:1080p:2160p = 5:3:1, I = 100, quarter or
+    10-50 % uniform-loss masks) replayed in real time against the
+    continuous-batching server and against the FIFO one-frame-per-launch loop.
+    Frame contents come from a pinned host pool of 3 frames per size; the
+    arrival times, sizes and order follow the seeded trace."""
+    import queue
+    import threading
+
+    import torch
+
+    import paper_2202_13926_amd as fsr
+    import synth
+
+    trace = synth.serving_trace(n_requests, rate_hz)
+    pool = {}
+    for req in trace:
+        key = (req.item.height, req.item.width)
+        if key in pool and len(pool[key]) >= 3:
+            continue
+        img, mask = req.item.inputs()
+        pool.setdefault(key, []).append((torch.from_numpy(img.astype(np.float32)).pin_memory(),
+                                         torch.from_numpy(mask).pin_memory()))
+    params = fsr.make_params()
+    out = {"workload": f"Poisson {rate_hz:g} frames/s, {n_requests} requests, 720p:1080p:2160p = 5:3:1, "
+                       "I=100, quarter or 10-50% uniform-loss masks, host-resident input frames",
+           "requests": n_requests, "hbm_budget_bytes": budget}
+    offered = sum(r.item.height * r.item.width for r in trace) / max(trace[-1].arrival_s, 1e-9) / 1e6
+    out["offered_mpx_s"] = round(offered, 2)
+    for name, mode, streams in (("continuous", fsr.FSR_SERVE_CONTINUOUS, 2),
+                                ("fifo_one_frame_per_launch", fsr.FSR_SERVE_FIFO, 1)):
+        cfg = fsr.make_server_config(hbm_budget=budget, max_inflight=64, max_batch=16,
+                                     streams=streams, mode=mode)
+        srv = fsr.Server(ctx, params, cfg)
+        for key, frames in pool.items():                     # warm-up
+            t = srv.submit(frames[0][0], frames[0][1], 100)
+            srv.wait(t)
+            srv.release(t)
+        q = queue.Queue()
+        rec = []
+
+        def reaper():
+            while True:
+                item = q.get()
+                if item is None:
+                    return
+                t, px = item
+                srv.wait(t)
+                sub, adm, lau, done = srv.timing(t)
+                srv.release(t)
+                rec.append((sub, adm, lau, done, px))
+
+        th = threading.Thread(target=reaper)
+        th.start()
+        t0 = time.perf_counter()
+        for k, req in enumerate(trace):
+            delay = t0 + req.arrival_s - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            frames = pool[(req.item.height, req.item.width)]
+            img, mask = frames[k % len(frames)]
+            q.put((srv.submit(img, mask, 100), req.item.height * req.item.width))
+        q.put(None)
+        th.join()
+        st = srv.stats()
+        srv.close()
+        a = np.array(rec)
+        lat = (a[:, 3] - a[:, 0]) * 1e3
+        span = a[:, 3].max() - a[:, 0].min()
+        out[name] = {"p50_ms": round(float(np.percentile(lat, 50)), 3),
+                     "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                     "max_ms": round(float(lat.max()), 3),
+                     "mean_queue_ms": round(float(np.mean(a[:, 1] - a[:, 0]) * 1e3), 3),
+                     "throughput_mpx_s": round(float(a[:, 4].sum() / span / 1e6), 2),
+                     "frames_per_launch": round(st["completed"] / max(st["launches"], 1), 3),
+                     "gpu_busy_frac": round(st["busy_s"] / span, 3),
+                     "peak_hbm_bytes": int(st["peak_bytes_in_use"])}
+    return out
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -256,6 +339,8 @@ def main():
     }
     if not args.no_batched:
         res["batched"] = bench_batched(ctx)
+    if args.serve_requests > 0:
+        res["served"] = bench_served(ctx, args.serve_requests)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(img32, mask, w, args.cpu_blocks)
     ctx.close()

@@ -201,6 +201,100 @@ FSR_API fsr_status fsr_batch_graph_create(fsr_context *ctx, const fsr_image_desc
 FSR_API fsr_status fsr_batch_graph_launch(fsr_batch_graph *graph, void *stream);
 FSR_API fsr_status fsr_batch_graph_destroy(fsr_batch_graph *graph);
 
+/* ------------------------------------------------------------------ serving */
+
+/* Where the pixels of a request live. */
+enum {
+    FSR_MEM_HOST = 0,     /* host memory (pinned memory gives asynchronous copies) */
+    FSR_MEM_DEVICE = 1    /* device memory of the server's device               */
+};
+
+/* How a server schedules admitted requests. */
+enum {
+    FSR_SERVE_CONTINUOUS = 0,  /* every launch takes all admitted, uploaded
+                                  requests (up to max_batch) as one batch; up to
+                                  `streams` launches overlap on the device while
+                                  new requests are admitted and uploaded       */
+    FSR_SERVE_FIFO = 1         /* reference loop: one request per launch, in
+                                  arrival order, upload and reconstruction in
+                                  one stream                                   */
+};
+
+typedef struct fsr_server_config {
+    size_t hbm_budget;      /* device bytes for request buffers; each admitted
+                               request holds image, mask and output
+                               (9 bytes per pixel, 256-byte aligned parts)     */
+    int32_t max_inflight;   /* requests admitted at once (1..4096)           */
+    int32_t max_batch;      /* requests per launch (1..max_inflight)          */
+    int32_t streams;        /* compute streams, 1 or 2                         */
+    int32_t mode;           /* FSR_SERVE_*                                     */
+    int32_t reserved[4];    /* must be 0                                       */
+} fsr_server_config;
+
+/* One frame to reconstruct.  The buffers must stay valid and unchanged until
+ * the request is done (fsr_server_poll reports it). */
+typedef struct fsr_request {
+    const float *image;
+    const uint8_t *mask;
+    int32_t height, width;
+    int64_t stride;         /* row stride of image and mask, elements          */
+    int32_t iterations;     /* I for this frame                                */
+    int32_t memory;         /* FSR_MEM_HOST or FSR_MEM_DEVICE                  */
+} fsr_request;
+
+typedef struct fsr_server_stats {
+    uint64_t submitted, admitted, completed, released, launches, rejected;
+    uint64_t bytes_in_use, peak_bytes_in_use;
+    double busy_s;          /* time with at least one launch in flight         */
+} fsr_server_stats;
+
+typedef struct fsr_server fsr_server;
+
+/*
+ * Creates a server with its own scheduler thread, copy stream, compute
+ * streams and a device arena of cfg->hbm_budget bytes on the context's
+ * device (method parameters are fixed per server; per-request I comes with
+ * each request).  Requests are admitted in arrival order while the arena and
+ * the in-flight limit allow; an admitted request is copied into the arena
+ * and reconstructed there, and its output stays in device memory until
+ * fetched or released.  Each result is bitwise identical to fsr_reconstruct
+ * on the same frame, whatever else shares its launch.
+ */
+FSR_API fsr_status fsr_server_create(fsr_context *ctx, const fsr_params *params,
+                                     const fsr_server_config *cfg, fsr_server **out);
+
+/* Queues a request; returns immediately with a ticket.  FSR_ERR_BUDGET if the
+ * frame alone exceeds the arena, FSR_ERR_INVALID_ARG for bad fields. */
+FSR_API fsr_status fsr_server_submit(fsr_server *srv, const fsr_request *req, uint64_t *ticket);
+
+/* *done = 1 once the reconstruction of `ticket` has finished on the device. */
+FSR_API fsr_status fsr_server_poll(fsr_server *srv, uint64_t ticket, int32_t *done);
+
+/* Blocks until `ticket` is done or timeout_ms passes (FSR_ERR_TIMEOUT);
+ * timeout_ms < 0 waits without limit. */
+FSR_API fsr_status fsr_server_wait(fsr_server *srv, uint64_t ticket, int32_t timeout_ms);
+
+/* Copies a finished result into `out` (row stride out_stride elements, host
+ * or device memory as given) and releases the request's arena space.
+ * FSR_ERR_NOT_READY if it has not finished. */
+FSR_API fsr_status fsr_server_result(fsr_server *srv, uint64_t ticket, float *out,
+                                     int64_t out_stride, int32_t memory);
+
+/* Releases a finished request without copying its result. */
+FSR_API fsr_status fsr_server_release(fsr_server *srv, uint64_t ticket);
+
+/* Timestamps (seconds on the host's steady clock) of a request: submission,
+ * admission, launch and observed completion (completion is observed by the
+ * scheduler thread, which polls the device every ~20 us while busy). */
+FSR_API fsr_status fsr_server_timing(fsr_server *srv, uint64_t ticket, double *submit_s,
+                                     double *admit_s, double *launch_s, double *done_s);
+
+FSR_API fsr_status fsr_server_get_stats(fsr_server *srv, fsr_server_stats *out);
+
+/* Waits for every admitted request to finish, stops the scheduler thread and
+ * frees the arena.  Requests still queued are dropped. */
+FSR_API fsr_status fsr_server_destroy(fsr_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,3 +11,7 @@ from .binding import (  # noqa: F401
     fsr_params_default, fsr_params_validate, fsr_reconstruct, fsr_reconstruct_batched, fsr_version,
     load_library, make_params, make_schedule, reconstruct,
 )
+from .binding import (  # noqa: F401
+    FSR_MEM_DEVICE, FSR_MEM_HOST, FSR_SERVE_CONTINUOUS, FSR_SERVE_FIFO, Server, fsr_request,
+    fsr_server_config, fsr_server_stats, make_server_config,
+)

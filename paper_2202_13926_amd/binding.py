@@ -59,6 +59,40 @@ def make_schedule(waves_per_group=1, chunk=0, groups_per_cu=10) -> fsr_batch_sch
     return fsr_batch_schedule(waves_per_group, chunk, groups_per_cu, 0)
 
 
+FSR_MEM_HOST = 0
+FSR_MEM_DEVICE = 1
+FSR_SERVE_CONTINUOUS = 0
+FSR_SERVE_FIFO = 1
+
+
+class fsr_server_config(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_inflight", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("streams", ctypes.c_int32),
+                ("mode", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+
+
+class fsr_request(ctypes.Structure):
+    _fields_ = [("image", ctypes.c_void_p), ("mask", ctypes.c_void_p), ("height", ctypes.c_int32),
+                ("width", ctypes.c_int32), ("stride", ctypes.c_int64),
+                ("iterations", ctypes.c_int32), ("memory", ctypes.c_int32)]
+
+
+class fsr_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("admitted", ctypes.c_uint64),
+                ("completed", ctypes.c_uint64), ("released", ctypes.c_uint64),
+                ("launches", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
+                ("bytes_in_use", ctypes.c_uint64), ("peak_bytes_in_use", ctypes.c_uint64),
+                ("busy_s", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def make_server_config(hbm_budget=4 << 30, max_inflight=64, max_batch=16, streams=2,
+                       mode=FSR_SERVE_CONTINUOUS) -> fsr_server_config:
+    return fsr_server_config(int(hbm_budget), max_inflight, max_batch, streams, mode)
+
+
 def make_params(block=4, border=14, iterations=100, rho=0.7, gamma=0.5, dft=FSR_DFT_FP32,
                 flags=0) -> fsr_params:
     return fsr_params(block, border, iterations, rho, gamma, dft, flags)
@@ -107,6 +141,17 @@ def load_library(path: str | None = None):
                                                   ctypes.c_size_t, ctypes.POINTER(vp)]),
         "fsr_batch_graph_launch": (ctypes.c_int, [vp, vp]),
         "fsr_batch_graph_destroy": (ctypes.c_int, [vp]),
+        "fsr_server_create": (ctypes.c_int, [vp, P, ctypes.POINTER(fsr_server_config),
+                                             ctypes.POINTER(vp)]),
+        "fsr_server_submit": (ctypes.c_int, [vp, ctypes.POINTER(fsr_request),
+                                             ctypes.POINTER(ctypes.c_uint64)]),
+        "fsr_server_poll": (ctypes.c_int, [vp, ctypes.c_uint64, ctypes.POINTER(i32)]),
+        "fsr_server_wait": (ctypes.c_int, [vp, ctypes.c_uint64, i32]),
+        "fsr_server_result": (ctypes.c_int, [vp, ctypes.c_uint64, vp, i64, i32]),
+        "fsr_server_release": (ctypes.c_int, [vp, ctypes.c_uint64]),
+        "fsr_server_timing": (ctypes.c_int, [vp, ctypes.c_uint64] + [ctypes.POINTER(ctypes.c_double)] * 4),
+        "fsr_server_get_stats": (ctypes.c_int, [vp, ctypes.POINTER(fsr_server_stats)]),
+        "fsr_server_destroy": (ctypes.c_int, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -339,6 +384,85 @@ class BatchGraph:
         if self._ptr:
             load_library().fsr_batch_graph_destroy(self._ptr)
             self._ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- serving
+class Server:
+    """A continuous-batching frame server (see fsr_server_create)."""
+
+    def __init__(self, ctx: Context, params: fsr_params, config: fsr_server_config):
+        self._ptr = ctypes.c_void_p()
+        _check(load_library().fsr_server_create(ctx.handle, ctypes.byref(params),
+                                                 ctypes.byref(config), ctypes.byref(self._ptr)))
+        self._ctx = ctx
+        self._keep = {}          # ticket -> buffers that must outlive the request
+
+    def submit(self, image, mask, iterations: int) -> int:
+        """Queue a frame held in torch tensors (host or device); returns a ticket."""
+        import torch
+        if image.dtype != torch.float32 or mask.dtype != torch.uint8 or image.dim() != 2 \
+                or mask.shape != image.shape:
+            raise FsrError(FSR_ERR_INVALID_ARG, "image float32 and mask uint8 of one 2-D shape")
+        H, W = image.shape
+        rows = {t.stride(0) if H > 1 else W for t in (image, mask)}
+        if len(rows) != 1 or any(W > 1 and t.stride(1) != 1 for t in (image, mask)):
+            raise FsrError(FSR_ERR_INVALID_ARG, "image and mask need unit column stride and one row stride")
+        if image.is_cuda != mask.is_cuda:
+            raise FsrError(FSR_ERR_INVALID_ARG, "image and mask must both be host or both device")
+        req = fsr_request(image.data_ptr(), mask.data_ptr(), H, W, rows.pop(), int(iterations),
+                          FSR_MEM_DEVICE if image.is_cuda else FSR_MEM_HOST)
+        t = ctypes.c_uint64()
+        _check(load_library().fsr_server_submit(self._ptr, ctypes.byref(req), ctypes.byref(t)))
+        self._keep[t.value] = (image, mask)
+        return int(t.value)
+
+    def poll(self, ticket: int) -> bool:
+        d = ctypes.c_int32()
+        _check(load_library().fsr_server_poll(self._ptr, ticket, ctypes.byref(d)))
+        return bool(d.value)
+
+    def wait(self, ticket: int, timeout_ms: int = -1) -> None:
+        _check(load_library().fsr_server_wait(self._ptr, ticket, int(timeout_ms)))
+
+    def result(self, ticket: int, out) -> None:
+        """Copy the finished frame into the 2-D float32 tensor ``out`` and release it."""
+        W = out.shape[1]
+        stride = out.stride(0) if out.shape[0] > 1 else W
+        _check(load_library().fsr_server_result(self._ptr, ticket, ctypes.c_void_p(out.data_ptr()),
+                                                stride, FSR_MEM_DEVICE if out.is_cuda else FSR_MEM_HOST))
+        self._keep.pop(ticket, None)
+
+    def release(self, ticket: int) -> None:
+        _check(load_library().fsr_server_release(self._ptr, ticket))
+        self._keep.pop(ticket, None)
+
+    def timing(self, ticket: int) -> tuple:
+        v = [ctypes.c_double() for _ in range(4)]
+        _check(load_library().fsr_server_timing(self._ptr, ticket, *[ctypes.byref(x) for x in v]))
+        return tuple(x.value for x in v)
+
+    def stats(self) -> dict:
+        st = fsr_server_stats()
+        _check(load_library().fsr_server_get_stats(self._ptr, ctypes.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if self._ptr:
+            load_library().fsr_server_destroy(self._ptr)
+            self._ptr = ctypes.c_void_p()
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
     def __del__(self):
         try:

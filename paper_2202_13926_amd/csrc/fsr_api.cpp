@@ -151,6 +151,7 @@ using namespace fsr;
 struct fsr_context {
     int device = 0;
     std::mutex mu;
+    std::mutex batch_mu;
     float* freq_w = nullptr;
     std::map<uint32_t, float*> rho_pow;   // keyed by the bits of rho
     fsr::BatchState batch;
@@ -195,6 +196,7 @@ fsr_status context_tables(fsr_context* ctx, float rho, BlockTables* out) {
 int context_device(const fsr_context* ctx) { return ctx->device; }
 BatchState& context_batch(fsr_context* ctx) { return ctx->batch; }
 std::mutex& context_mutex(fsr_context* ctx) { return ctx->mu; }
+std::mutex& context_batch_mutex(fsr_context* ctx) { return ctx->batch_mu; }
 
 }  // namespace fsr
 

@@ -151,31 +151,31 @@ fsr_status prepare(fsr_context* ctx, const fsr_image_desc* descs, int32_t n, con
 }
 
 // Copies the descriptor table into the workspace, ordered on `stream`,
-// through the context's pinned staging buffer.
-fsr_status upload_async(fsr_context* ctx, const BatchPlan& plan, void* workspace, hipStream_t stream) {
+// through a pinned staging slot (the previous copy out of it must be done
+// before it is overwritten).
+fsr_status upload_async(const BatchPlan& plan, void* workspace, hipStream_t stream,
+                        StagingSlot* slot) {
     const size_t bytes = plan.table.size() * sizeof(DevDesc);
     if (bytes == 0) return FSR_OK;
-    BatchState& bs = context_batch(ctx);
-    std::lock_guard<std::mutex> lock(context_mutex(ctx));
     hipError_t e;
-    if (bs.staging_done) {                       // the previous upload must have read the staging
-        if ((e = hipEventSynchronize(bs.staging_done)) != hipSuccess) return hip_fail(e, "hipEventSynchronize");
-    } else if ((e = hipEventCreateWithFlags(&bs.staging_done, hipEventDisableTiming)) != hipSuccess) {
+    if (slot->done) {
+        if ((e = hipEventSynchronize(slot->done)) != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    } else if ((e = hipEventCreateWithFlags(&slot->done, hipEventDisableTiming)) != hipSuccess) {
         return hip_fail(e, "hipEventCreate");
     }
-    if (bs.staging_bytes < bytes) {
-        if (bs.staging) (void)hipHostFree(bs.staging);
-        bs.staging = nullptr;
-        bs.staging_bytes = 0;
-        if ((e = hipHostMalloc(&bs.staging, bytes, hipHostMallocDefault)) != hipSuccess)
+    if (slot->bytes < bytes) {
+        if (slot->host) (void)hipHostFree(slot->host);
+        slot->host = nullptr;
+        slot->bytes = 0;
+        if ((e = hipHostMalloc(&slot->host, bytes, hipHostMallocDefault)) != hipSuccess)
             return errorf(FSR_ERR_OUT_OF_MEMORY, "hipHostMalloc(%zu): %s", bytes, hipGetErrorString(e));
-        bs.staging_bytes = bytes;
+        slot->bytes = bytes;
     }
-    std::memcpy(bs.staging, plan.table.data(), bytes);
-    e = hipMemcpyAsync(static_cast<char*>(workspace) + kCtrlBytes, bs.staging, bytes,
+    std::memcpy(slot->host, plan.table.data(), bytes);
+    e = hipMemcpyAsync(static_cast<char*>(workspace) + kCtrlBytes, slot->host, bytes,
                        hipMemcpyHostToDevice, stream);
     if (e != hipSuccess) return hip_fail(e, "descriptor upload");
-    if ((e = hipEventRecord(bs.staging_done, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    if ((e = hipEventRecord(slot->done, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     return FSR_OK;
 }
 
@@ -187,16 +187,44 @@ fsr_status launch_prepared(const Prepared& prep, hipStream_t stream) {
 
 }  // namespace
 
-void release_batch_state(BatchState& st) {
-    if (st.staging_done) {
-        (void)hipEventSynchronize(st.staging_done);
-        (void)hipEventDestroy(st.staging_done);
+void release_staging(StagingSlot& slot) {
+    if (slot.done) {
+        (void)hipEventSynchronize(slot.done);
+        (void)hipEventDestroy(slot.done);
     }
-    if (st.staging) (void)hipHostFree(st.staging);
-    st.staging = nullptr;
-    st.staging_bytes = 0;
-    st.staging_done = nullptr;
+    if (slot.host) (void)hipHostFree(slot.host);
+    slot = StagingSlot{};
+}
+
+void release_batch_state(BatchState& st) {
+    release_staging(st.staging);
     st.tuned.clear();
+}
+
+fsr_status batched_enqueue(fsr_context* ctx, const fsr_image_desc* descs, int32_t n,
+                           const fsr_params* params, const fsr_batch_schedule* schedule,
+                           void* workspace, size_t ws_bytes, hipStream_t stream,
+                           StagingSlot* slot, std::mutex* slot_mutex) {
+    BatchPlan plan;
+    Prepared prep;
+    fsr_status st = prepare(ctx, descs, n, params, schedule, workspace, ws_bytes, &plan, &prep);
+    if (st != FSR_OK) return st;
+    if (plan.total_blocks == 0) return FSR_OK;
+    DeviceGuard g(context_device(ctx));
+    if (g.error() != hipSuccess) return hip_fail(g.error(), "hipSetDevice");
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(stream, &cap);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
+    if (cap != hipStreamCaptureStatusNone)
+        return errorf(FSR_ERR_UNSUPPORTED, "stream is being captured: use fsr_batch_graph_create");
+    if ((st = context_tables(ctx, params->rho, &prep.launch.tab)) != FSR_OK) return st;
+    if (slot_mutex) {
+        std::lock_guard<std::mutex> lock(*slot_mutex);
+        if ((st = upload_async(plan, workspace, stream, slot)) != FSR_OK) return st;
+    } else if ((st = upload_async(plan, workspace, stream, slot)) != FSR_OK) {
+        return st;
+    }
+    return launch_prepared(prep, stream);
 }
 
 }  // namespace fsr
@@ -221,22 +249,10 @@ fsr_status fsr_batched_workspace_size(int32_t n_images, size_t* bytes) {
 fsr_status fsr_reconstruct_batched(fsr_context* ctx, const fsr_image_desc* descs, int32_t n_images,
                                    const fsr_params* params, const fsr_batch_schedule* schedule,
                                    void* workspace, size_t workspace_bytes, void* stream) {
-    BatchPlan plan;
-    Prepared prep;
-    fsr_status st = prepare(ctx, descs, n_images, params, schedule, workspace, workspace_bytes, &plan, &prep);
-    if (st != FSR_OK) return st;
-    if (plan.total_blocks == 0) return FSR_OK;
-    DeviceGuard g(context_device(ctx));
-    if (g.error() != hipSuccess) return hip_fail(g.error(), "hipSetDevice");
-    hipStream_t s = (hipStream_t)stream;
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    hipError_t e = hipStreamIsCapturing(s, &cap);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
-    if (cap != hipStreamCaptureStatusNone)
-        return errorf(FSR_ERR_UNSUPPORTED, "stream is being captured: use fsr_batch_graph_create");
-    if ((st = context_tables(ctx, params->rho, &prep.launch.tab)) != FSR_OK) return st;
-    if ((st = upload_async(ctx, plan, workspace, s)) != FSR_OK) return st;
-    return launch_prepared(prep, s);
+    if (!ctx) return errorf(FSR_ERR_INVALID_ARG, "context is NULL");
+    return batched_enqueue(ctx, descs, n_images, params, schedule, workspace, workspace_bytes,
+                           (hipStream_t)stream, &context_batch(ctx).staging,
+                           &context_batch_mutex(ctx));
 }
 
 fsr_status fsr_batch_autotune(fsr_context* ctx, const fsr_image_desc* descs, int32_t n_images,
@@ -259,7 +275,10 @@ fsr_status fsr_batch_autotune(fsr_context* ctx, const fsr_image_desc* descs, int
     if (g.error() != hipSuccess) return hip_fail(g.error(), "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
     if ((st = context_tables(ctx, params->rho, &prep.launch.tab)) != FSR_OK) return st;
-    if ((st = upload_async(ctx, plan, workspace, s)) != FSR_OK) return st;
+    {
+        std::lock_guard<std::mutex> lock(context_batch_mutex(ctx));
+        if ((st = upload_async(plan, workspace, s, &context_batch(ctx).staging)) != FSR_OK) return st;
+    }
     int cus = 0;
     if ((st = cu_count(ctx, &cus)) != FSR_OK) return st;
     hipEvent_t t0 = nullptr, t1 = nullptr;

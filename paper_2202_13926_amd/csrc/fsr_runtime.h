@@ -28,18 +28,35 @@ private:
     hipError_t err_ = hipSuccess;
 };
 
-// Per-context state of the batched path: pinned staging for descriptor
-// uploads, the event that marks the last upload as consumed, the device's
-// compute-unit count and the schedules chosen by the autotuner.
+// Pinned host buffer through which a batch's descriptors reach the device,
+// and the event that marks the last copy out of it as done.
+struct StagingSlot {
+    void* host = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;
+};
+
+void release_staging(StagingSlot& slot);
+
+// Per-context state of the batched path: the staging slot of
+// fsr_reconstruct_batched, the device's compute-unit count and the
+// schedules chosen by the autotuner.
 struct BatchState {
-    void* staging = nullptr;
-    size_t staging_bytes = 0;
-    hipEvent_t staging_done = nullptr;
+    StagingSlot staging;
     int cu_count = 0;
     std::map<uint64_t, fsr_batch_schedule> tuned;
 };
 
 void release_batch_state(BatchState& st);
+
+// Validates a batch and enqueues descriptor upload (through `slot`, under
+// `slot_mutex` when given) plus the batched kernel on `stream`.  Nothing is
+// touched before validation passes.  Shared by fsr_reconstruct_batched and
+// the server.
+fsr_status batched_enqueue(fsr_context* ctx, const fsr_image_desc* descs, int32_t n,
+                           const fsr_params* params, const fsr_batch_schedule* schedule,
+                           void* workspace, size_t ws_bytes, hipStream_t stream,
+                           StagingSlot* slot, std::mutex* slot_mutex);
 
 fsr_status set_error(fsr_status st, const char* msg);
 fsr_status errorf(fsr_status st, const char* fmt, ...);
@@ -52,5 +69,6 @@ fsr_status context_tables(fsr_context* ctx, float rho, BlockTables* out);
 int context_device(const fsr_context* ctx);
 BatchState& context_batch(fsr_context* ctx);
 std::mutex& context_mutex(fsr_context* ctx);
+std::mutex& context_batch_mutex(fsr_context* ctx);   // guards the batch staging slot
 
 }  // namespace fsr

@@ -119,3 +119,26 @@ def test_batched_validates_before_touching_the_device(lib):
                                       ctypes.byref(out)) == E
     assert lib.fsr_batch_graph_launch(None, None) == E
     assert lib.fsr_batch_graph_destroy(None) == binding.FSR_OK
+
+
+def test_server_config_validated_before_touching_the_device(lib):
+    p = fsr.make_params()
+    out = ctypes.c_void_p()
+    fake_ctx = ctypes.c_void_p(0x1000)       # never dereferenced: validation fails first
+    E = binding.FSR_ERR_INVALID_ARG
+    bad = [binding.make_server_config(hbm_budget=100), binding.make_server_config(max_inflight=0),
+           binding.make_server_config(max_inflight=8, max_batch=9), binding.make_server_config(streams=3),
+           binding.make_server_config(mode=5)]
+    cfg = binding.make_server_config()
+    cfg.reserved[2] = 1
+    bad.append(cfg)
+    for c in bad:
+        assert lib.fsr_server_create(fake_ctx, ctypes.byref(p), ctypes.byref(c), ctypes.byref(out)) == E
+    c = binding.make_server_config()
+    assert lib.fsr_server_create(None, ctypes.byref(p), ctypes.byref(c), ctypes.byref(out)) == E
+    assert lib.fsr_server_create(fake_ctx, ctypes.byref(fsr.make_params(block=4, border=6)),
+                                 ctypes.byref(c), ctypes.byref(out)) == binding.FSR_ERR_UNSUPPORTED
+    t = ctypes.c_uint64()
+    req = binding.fsr_request(0x1000, 0x2000, 8, 8, 8, 10, 0)
+    assert lib.fsr_server_submit(None, ctypes.byref(req), ctypes.byref(t)) == E
+    assert lib.fsr_server_destroy(None) == binding.FSR_OK
