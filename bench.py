@@ -76,6 +76,8 @@ def parse():
                     help="blocks in the oracle's timed sample")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 64-image batched comparison")
+    ap.add_argument("--serve-max-batch", type=int, default=2,
+                    help="frames per launch of the continuous-batching server")
     ap.add_argument("--serve-requests", type=int, default=2400,
                     help="requests of the served comparison (0 skips it); the stated workload "
                          "is 10,000 (about 42 s per mode)")
@@ -174,7 +176,8 @@ def bench_batched(ctx, steps: int = 5):
             "speedup_vs_plain_loop": round(plain_ms / min(batched_ms, graph_ms), 3)}
 
 
-def bench_served(ctx, n_requests: int, rate_hz: float = 240.0, budget: int = 4 << 30):
+def bench_served(ctx, n_requests: int, rate_hz: float = 240.0, budget: int = 4 << 30,
+                 max_batch: int = 2):
     """Poisson stream of frames (720p:1080p:2160p = 5:3:1, I = 100, quarter or
     10-50 % uniform-loss masks) replayed in real time against the
     continuous-batching server and against the FIFO one-frame-per-launch loop.
@@ -200,12 +203,13 @@ def bench_served(ctx, n_requests: int, rate_hz: float = 240.0, budget: int = 4 <
     params = fsr.make_params()
     out = {"workload": f"Poisson {rate_hz:g} frames/s, {n_requests} requests, 720p:1080p:2160p = 5:3:1, "
                        "I=100, quarter or 10-50% uniform-loss masks, host-resident input frames",
-           "requests": n_requests, "hbm_budget_bytes": budget}
+           "requests": n_requests, "hbm_budget_bytes": budget, "max_batch": max_batch}
     offered = sum(r.item.height * r.item.width for r in trace) / max(trace[-1].arrival_s, 1e-9) / 1e6
     out["offered_mpx_s"] = round(offered, 2)
     for name, mode, streams in (("continuous", fsr.FSR_SERVE_CONTINUOUS, 2),
                                 ("fifo_one_frame_per_launch", fsr.FSR_SERVE_FIFO, 1)):
-        cfg = fsr.make_server_config(hbm_budget=budget, max_inflight=64, max_batch=16,
+        cfg = fsr.make_server_config(hbm_budget=budget, max_inflight=64,
+                                     max_batch=max_batch if mode == fsr.FSR_SERVE_CONTINUOUS else 1,
                                      streams=streams, mode=mode)
         srv = fsr.Server(ctx, params, cfg)
         for key, frames in pool.items():                     # warm-up
@@ -340,7 +344,7 @@ def main():
     if not args.no_batched:
         res["batched"] = bench_batched(ctx)
     if args.serve_requests > 0:
-        res["served"] = bench_served(ctx, args.serve_requests)
+        res["served"] = bench_served(ctx, args.serve_requests, max_batch=args.serve_max_batch)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(img32, mask, w, args.cpu_blocks)
     ctx.close()
