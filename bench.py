@@ -76,6 +76,8 @@ def parse():
                     help="blocks in the oracle's timed sample")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 64-image batched comparison")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the split-bf16 vs FP32-FFT comparison on the 3840x2160 frame")
     ap.add_argument("--serve-max-batch", type=int, default=2,
                     help="frames per launch of the continuous-batching server")
     ap.add_argument("--serve-requests", type=int, default=2400,
@@ -116,10 +118,57 @@ def cpu_baseline(img32, mask, w, n_blocks_sample):
                       f"FP64 C oracle, OpenMP over blocks, {dt:.2f} s wall"}
 
 
+def bench_precision(ctx, steps: int = 3):
+    """3840x2160 concealment frame (25 % of 16x16 macroblocks dropped, 10 %
+    uniform loss elsewhere), I = 200: the FP32-FFT path against the split-bf16
+    matrix-core DFTs, timed on the same buffers, each scored against the
+    ground-truth frame, and the two outputs against each other."""
+    import torch
+
+    import paper_2202_13926_amd as fsr
+    import synth
+    from synth.metrics import psnr
+
+    w = synth.workload("uhd_concealment")
+    img, mask = w.inputs()
+    img32 = img.astype(np.float32)
+    dev = torch.device("cuda:0")
+    ti = torch.from_numpy(img32).to(dev)
+    tm = torch.from_numpy(mask).to(dev)
+    stream = torch.cuda.current_stream(dev)
+    res = {"workload": "uhd_concealment: 3840x2160, 25% of 16x16 macroblocks dropped + 10% uniform "
+                       "loss, B=4 L=14 (S=32), I=200, rho=0.7, gamma=0.5",
+           "blocks": w.n_blocks}
+    outs = {}
+    for tag, dft in (("fp32_fft", fsr.FSR_DFT_FP32), ("split_bf16", fsr.FSR_DFT_SPLIT_BF16)):
+        p = fsr.make_params(block=w.block, border=w.border, iterations=w.iterations, rho=w.rho,
+                            gamma=w.gamma, dft=dft)
+        o = torch.empty_like(ti)
+        fsr.fsr_reconstruct(ctx, ti, tm, o, p, None, stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            fsr.fsr_reconstruct(ctx, ti, tm, o, p, None, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        g = o.cpu().numpy()
+        outs[tag] = g
+        res[tag] = {"ms": round(ms, 3), "mpx_s": round(img.size / ms / 1e3, 2),
+                    "psnr_missing_db": round(psnr(img32, g, mask == 0), 4)}
+    d = np.abs(outs["fp32_fft"] - outs["split_bf16"])[mask == 0]
+    res["split_bf16_vs_fp32_fft"] = {"max_abs": round(float(d.max()), 5),
+                                     "frac_le_1_code": round(float(np.mean(d <= 1.0)), 6)}
+    return res
+
+
 def bench_batched(ctx, steps: int = 5):
     """64 uneven images (256x256 .. 1920x1080, quarter or 10-50 % uniform loss,
-    I in {50, 100, 200}): the tuned batched launch, its graph replay and the
-    plain loop of one fsr_reconstruct launch per image, on the same buffers."""
+    I in {50, 100, 200}) with split-bf16 DFTs and FP32 iterations: the tuned
+    batched launch, its graph replay and the plain loop of one fsr_reconstruct
+    launch per image, on the same buffers; the graph replay with FP32 FFTs for
+    reference."""
     import torch
 
     import paper_2202_13926_amd as fsr
@@ -135,7 +184,7 @@ def bench_batched(ctx, steps: int = 5):
         items.append(fsr.BatchItem(ti, tm, torch.empty_like(ti), sp.iterations))
         pixels += img.size
         work += fsr.fsr_num_blocks(sp.height, sp.width, 4) * sp.iterations
-    params = fsr.make_params()
+    params = fsr.make_params(dft=fsr.FSR_DFT_SPLIT_BF16)
     ws = fsr.Workspace(len(items), dev)
     stream = torch.cuda.current_stream(dev)
     t0 = time.perf_counter()
@@ -157,22 +206,27 @@ def bench_batched(ctx, steps: int = 5):
     graph = fsr.BatchGraph(ctx, items, params, fsr.Workspace(len(items), dev), best)
     graph_ms = timed(lambda: graph.launch(stream), steps)
     graph.close()
+    graph32 = fsr.BatchGraph(ctx, items, fsr.make_params(), fsr.Workspace(len(items), dev), best)
+    graph32_ms = timed(lambda: graph32.launch(stream), steps)
+    graph32.close()
 
     def plain_loop():
         for it in items:
-            p = fsr.make_params(iterations=it.iterations)
+            p = fsr.make_params(iterations=it.iterations, dft=fsr.FSR_DFT_SPLIT_BF16)
             fsr.fsr_reconstruct(ctx, it.image, it.mask, it.out, p, None, stream)
 
     plain_ms = timed(plain_loop, max(2, steps // 2))
     mpx = pixels / 1e6
     return {"workload": "64 uneven images 256x256..1920x1080, quarter or 10-50% uniform loss, "
                         "I in {50,100,200}, S=32, rho=0.7, gamma=0.5",
+            "dft": "split-bf16 (3 terms) on the matrix cores, FP32 iterations",
             "pixels": pixels, "block_iterations": int(work),
             "schedule": {"waves_per_group": best.waves_per_group, "chunk": best.chunk,
                          "groups_per_cu": best.groups_per_cu}, "autotune_s": round(tune_s, 3),
             "batched_ms": round(batched_ms, 3), "batched_mpx_s": round(mpx / batched_ms * 1e3, 2),
             "graph_ms": round(graph_ms, 3), "graph_mpx_s": round(mpx / graph_ms * 1e3, 2),
             "plain_loop_ms": round(plain_ms, 3), "plain_loop_mpx_s": round(mpx / plain_ms * 1e3, 2),
+            "graph_fp32_fft_ms": round(graph32_ms, 3),
             "speedup_vs_plain_loop": round(plain_ms / min(batched_ms, graph_ms), 3)}
 
 
@@ -343,6 +397,8 @@ def main():
     }
     if not args.no_batched:
         res["batched"] = bench_batched(ctx)
+    if not args.no_precision:
+        res["precision"] = bench_precision(ctx)
     if args.serve_requests > 0:
         res["served"] = bench_served(ctx, args.serve_requests, max_batch=args.serve_max_batch)
     if not args.no_cpu_baseline:

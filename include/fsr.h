@@ -55,10 +55,14 @@ typedef enum fsr_status {
     FSR_ERR_NOT_READY = 7      /* polled work has not finished yet         */
 } fsr_status;
 
-/* How the forward block DFTs are computed. */
+/* How the two forward block DFTs of Eq. 7 are computed; the iterations are
+ * FP32 either way.  FSR_DFT_SPLIT_BF16 runs them as 32 x 32 DFT-matrix
+ * products on the matrix cores (bf16 inputs, FP32 accumulation) with every
+ * operand split into three bf16 terms (hi + mid + lo, 6 products per real
+ * product), which keeps the spectra as accurate as the FP32 FFT's. */
 enum {
     FSR_DFT_FP32 = 0,        /* FP32 in-register FFT on the vector ALUs    */
-    FSR_DFT_SPLIT_BF16 = 1   /* hi+lo bf16 DFT-matrix products on MFMA     */
+    FSR_DFT_SPLIT_BF16 = 1   /* split-bf16 DFT-matrix products on MFMA     */
 };
 
 /*
@@ -168,7 +172,7 @@ FSR_API fsr_status fsr_batched_workspace_size(int32_t n_images, size_t *bytes);
  *              once the call returns)
  *   params     block, border, rho, gamma, dft shared by all images
  *   schedule   NULL: the schedule fsr_batch_autotune chose for a batch of
- *              this size class on this context, else a plain grid
+ *              this size class and dft mode on this context, else a plain grid
  *   workspace  device memory of >= fsr_batched_workspace_size bytes; it must
  *              not be in use by another call that has not completed
  * Asynchronous on `stream`; must not be called while `stream` is being
@@ -181,7 +185,7 @@ FSR_API fsr_status fsr_reconstruct_batched(fsr_context *ctx, const fsr_image_des
 
 /* Times the batch under a fixed list of candidate schedules (each run
  * reconstructs the batch, so outputs are written), stores the fastest on the
- * context for this batch's size class and returns it in *best.  Blocks the
+ * context for this batch's size class and dft mode and returns it in *best.  Blocks the
  * host until the timing runs finish. */
 FSR_API fsr_status fsr_batch_autotune(fsr_context *ctx, const fsr_image_desc *descs,
                                       int32_t n_images, const fsr_params *params,

@@ -26,6 +26,10 @@ FLAGS = [
     "-fvisibility=hidden", "-Wall",
     # packed FP32 instructions stay off: the scalar forms are what is validated
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core accumulators in ordinary VGPRs: the DFT's accumulators are
+    # short-lived, and AGPR copies would push the kernel past 168 registers
+    # (three wavefronts per SIMD)
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 

@@ -144,6 +144,61 @@ static std::vector<float> host_freq_w() {
     return t;
 }
 
+// bf16 bit pattern nearest to a float (round to nearest, ties to even).
+static uint16_t bf16_bits(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, sizeof u);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+static float bf16_value(uint16_t b) {
+    const uint32_t u = (uint32_t)b << 16;
+    float f;
+    std::memcpy(&f, &u, sizeof f);
+    return f;
+}
+
+// Operands of the DFT-matrix products of the split-bf16 transform.  The
+// 32-point DFT matrix F[m][k] = exp(-j 2 pi m k / 32) (exactly symmetric in
+// sign and index) is split per entry into bf16 terms: term 0 = bf16(F),
+// term i = bf16 of what terms 0 .. i-1 leave.  Entry [part][q][term][lane][v]
+// is part (Re F, Im F) of
+// F[16 q + 8 (v / 4) + 4 (lane / 32) + v % 4][lane % 32]: the B operand of
+// K-step q of both matrix products in the device transform.
+static void dft_table(std::vector<uint16_t>& t) {
+    const double pi = 3.14159265358979323846;
+    double fr[kS], fi[kS];                   // exp(-j 2 pi q / 32), exact symmetries
+    for (int q = 0; q < kS; ++q) {
+        const int a = q / 8, r = q % 8;
+        const int rr = r <= 4 ? r : 8 - r;
+        double c = std::cos(2.0 * pi * rr / kS), sn = std::sin(2.0 * pi * rr / kS);
+        if (rr == 4) sn = c;
+        if (r > 4) std::swap(c, sn);
+        switch (a) {
+        case 0: fr[q] = c; fi[q] = -sn; break;
+        case 1: fr[q] = -sn; fi[q] = -c; break;
+        case 2: fr[q] = -c; fi[q] = sn; break;
+        default: fr[q] = sn; fi[q] = c; break;
+        }
+    }
+    t.assign(kMfmaDftElems, 0);
+    for (int part = 0; part < 2; ++part)
+        for (int q = 0; q < 2; ++q)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int v = 0; v < 8; ++v) {
+                    const int n = 16 * q + 8 * (v / 4) + 4 * (lane / 32) + v % 4, l = lane % 32;
+                    const int e = (n * l) % kS;
+                    const double f = part == 0 ? fr[e] : fi[e];
+                    double rest = f;
+                    for (int term = 0; term < kMfmaMaxTerms; ++term) {
+                        const uint16_t b = bf16_bits((float)rest);
+                        t[((size_t)((part * 2 + q) * kMfmaMaxTerms + term) * 64 + lane) * 8 + v] = b;
+                        rest -= (double)bf16_value(b);
+                    }
+                }
+}
+
 }  // namespace fsr
 
 using namespace fsr;
@@ -153,6 +208,7 @@ struct fsr_context {
     std::mutex mu;
     std::mutex batch_mu;
     float* freq_w = nullptr;
+    uint16_t* mfma_tab = nullptr;          // split-bf16 DFT operands
     std::map<uint32_t, float*> rho_pow;   // keyed by the bits of rho
     fsr::BatchState batch;
 };
@@ -173,6 +229,19 @@ fsr_status context_tables(fsr_context* ctx, float rho, BlockTables* out) {
         }
         ctx->freq_w = d;
     }
+    if (!ctx->mfma_tab) {
+        std::vector<uint16_t> t;
+        dft_table(t);
+        uint16_t* d = nullptr;
+        hipError_t e = hipMalloc(&d, t.size() * sizeof(uint16_t));
+        if (e != hipSuccess) return fail(FSR_ERR_OUT_OF_MEMORY, "hipMalloc(dft table): %s", hipGetErrorString(e));
+        e = hipMemcpy(d, t.data(), t.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(d);
+            return hip_fail(e, "upload of dft table");
+        }
+        ctx->mfma_tab = d;
+    }
     uint32_t key;
     std::memcpy(&key, &rho, sizeof key);
     auto it = ctx->rho_pow.find(key);
@@ -190,6 +259,7 @@ fsr_status context_tables(fsr_context* ctx, float rho, BlockTables* out) {
     }
     out->rho_pow = it->second;
     out->freq_w = ctx->freq_w;
+    out->mfma_dft = ctx->mfma_tab;
     return FSR_OK;
 }
 
@@ -260,6 +330,7 @@ fsr_status fsr_context_destroy(fsr_context* ctx) {
         DeviceGuard g(ctx->device);
         release_batch_state(ctx->batch);
         if (ctx->freq_w) (void)hipFree(ctx->freq_w);
+        if (ctx->mfma_tab) (void)hipFree(ctx->mfma_tab);
         for (auto& kv : ctx->rho_pow) (void)hipFree(kv.second);
     }
     delete ctx;
@@ -275,8 +346,6 @@ fsr_status fsr_reconstruct(fsr_context* ctx, const float* image, const uint8_t* 
     if ((st = check_supported(params)) != FSR_OK) return st;
     if ((st = validate_image(image, mask, out, height, width, stride, params->block)) != FSR_OK)
         return st;
-    if (params->dft != FSR_DFT_FP32)
-        return fail(FSR_ERR_UNSUPPORTED, "fsr_reconstruct runs the FP32 DFT; use the batched path for split-bf16");
 
     DeviceGuard g(ctx->device);
     if (g.error() != hipSuccess) return hip_fail(g.error(), "hipSetDevice");
@@ -296,6 +365,7 @@ fsr_status fsr_reconstruct(fsr_context* ctx, const float* image, const uint8_t* 
     p.border = params->border;
     p.gamma = params->gamma;
     p.n_blocks = fsr_num_blocks(height, width, params->block);
+    p.dft = params->dft == FSR_DFT_SPLIT_BF16 ? 1 : 0;
     hipError_t e = launch_plain(p, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "launch of the reconstruction kernel");
     return FSR_OK;

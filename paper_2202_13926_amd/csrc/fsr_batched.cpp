@@ -84,10 +84,12 @@ fsr_status plan_batch(const fsr_image_desc* descs, int32_t n, const fsr_params* 
 }
 
 // Size class of a batch: log2 of its work and its largest iteration count.
-uint64_t size_class(const BatchPlan& plan) {
+// Key of the tuned-schedule table: log2 of the batch's work, the DFT mode
+// (the two kernels differ in register use) and the largest iteration count.
+uint64_t size_class(const BatchPlan& plan, int32_t dft) {
     uint64_t w = 0;
     for (double x = plan.work; x >= 2.0; x /= 2.0) ++w;
-    return (w << 32) | (uint64_t)(uint32_t)plan.max_iterations;
+    return (w << 40) | ((uint64_t)(uint32_t)dft << 32) | (uint64_t)(uint32_t)plan.max_iterations;
 }
 
 fsr_batch_schedule default_schedule() { return fsr_batch_schedule{1, 0, 10, 0}; }
@@ -118,8 +120,6 @@ fsr_status prepare(fsr_context* ctx, const fsr_image_desc* descs, int32_t n, con
     fsr_status st = validate_params(params);
     if (st != FSR_OK) return st;
     if ((st = check_supported(params)) != FSR_OK) return st;
-    if (params->dft != FSR_DFT_FP32)
-        return errorf(FSR_ERR_UNSUPPORTED, "this build's batched path runs the FP32 DFT");
     if ((st = check_schedule(schedule)) != FSR_OK) return st;
     if ((st = plan_batch(descs, n, params, plan)) != FSR_OK) return st;
     if (!workspace && n > 0) return errorf(FSR_ERR_INVALID_ARG, "workspace is NULL");
@@ -133,12 +133,13 @@ fsr_status prepare(fsr_context* ctx, const fsr_image_desc* descs, int32_t n, con
     prep->launch.block = params->block;
     prep->launch.border = params->border;
     prep->launch.gamma = params->gamma;
+    prep->launch.dft = params->dft == FSR_DFT_SPLIT_BF16 ? 1 : 0;
     if (schedule) {
         prep->schedule = *schedule;
     } else {
         BatchState& bs = context_batch(ctx);
         std::lock_guard<std::mutex> lock(context_mutex(ctx));
-        auto it = bs.tuned.find(size_class(*plan));
+        auto it = bs.tuned.find(size_class(*plan, params->dft));
         prep->schedule = it != bs.tuned.end() ? it->second : default_schedule();
     }
     prep->launch.chunk = prep->schedule.chunk;
@@ -308,7 +309,7 @@ fsr_status fsr_batch_autotune(fsr_context* ctx, const fsr_image_desc* descs, int
     (void)hipEventDestroy(t1);
     if (st != FSR_OK) return st;
     std::lock_guard<std::mutex> lock(context_mutex(ctx));
-    context_batch(ctx).tuned[size_class(plan)] = *best;
+    context_batch(ctx).tuned[size_class(plan, params->dft)] = *best;
     return FSR_OK;
 }
 

@@ -29,6 +29,7 @@ __device__ __forceinline__ void locate(const BatchLaunch& p, int64_t g, int& img
     end = lo + 1 < p.n_images ? p.descs[lo + 1].block_begin : p.total_blocks;
 }
 
+template <int kDft>
 __device__ __forceinline__ void batch_block(const BatchLaunch& p, int64_t g, int img, float* lds) {
     const DevDesc& d = p.descs[img];
     const int64_t local = g - d.block_begin;
@@ -43,10 +44,10 @@ __device__ __forceinline__ void batch_block(const BatchLaunch& p, int64_t g, int
     jb.by = (int32_t)(local / d.nbx);
     jb.bx = (int32_t)(local % d.nbx);
     jb.iterations = d.iterations;
-    reconstruct_block(jb, p.block, p.border, p.gamma, p.tab, lds);
+    reconstruct_block<kDft>(jb, p.block, p.border, p.gamma, p.tab, lds);
 }
 
-template <int kWaves>
+template <int kWaves, int kDft>
 __global__ __launch_bounds__(64 * kWaves) void fsr_batched_s32(BatchLaunch p) {
     __shared__ float lds[kWaves * kLdsFloats];
     // wave-uniform by construction; readfirstlane lets the compiler see it,
@@ -76,9 +77,21 @@ __global__ __launch_bounds__(64 * kWaves) void fsr_batched_s32(BatchLaunch p) {
             if (end > p.total_blocks) end = p.total_blocks;
         }
         locate(p, next, img, img_begin, img_end);
-        batch_block(p, next, img, mine);
+        batch_block<kDft>(p, next, img, mine);
         ++next;
     }
+}
+
+template <int kDft>
+static hipError_t launch_waves(const BatchLaunch& p, int waves_per_group, dim3 grid, dim3 block,
+                               hipStream_t stream) {
+    switch (waves_per_group) {
+    case 1: hipLaunchKernelGGL((fsr_batched_s32<1, kDft>), grid, block, 0, stream, p); break;
+    case 2: hipLaunchKernelGGL((fsr_batched_s32<2, kDft>), grid, block, 0, stream, p); break;
+    case 4: hipLaunchKernelGGL((fsr_batched_s32<4, kDft>), grid, block, 0, stream, p); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_batched(const BatchLaunch& p, int waves_per_group, int64_t groups,
@@ -90,13 +103,8 @@ hipError_t launch_batched(const BatchLaunch& p, int waves_per_group, int64_t gro
         groups = (p.total_blocks + waves_per_group - 1) / waves_per_group;
     }
     const dim3 grid((unsigned)groups), block(64 * waves_per_group);
-    switch (waves_per_group) {
-    case 1: hipLaunchKernelGGL(fsr_batched_s32<1>, grid, block, 0, stream, p); break;
-    case 2: hipLaunchKernelGGL(fsr_batched_s32<2>, grid, block, 0, stream, p); break;
-    case 4: hipLaunchKernelGGL(fsr_batched_s32<4>, grid, block, 0, stream, p); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    if (p.dft == kDftSplitBf16) return launch_waves<kDftSplitBf16>(p, waves_per_group, grid, block, stream);
+    return launch_waves<kDftFft32>(p, waves_per_group, grid, block, stream);
 }
 
 }  // namespace fsr

@@ -4,7 +4,8 @@
 //   gather     support tile at (by*B - L, bx*B - L); pixels outside the image
 //              or masked out are unknown: f~ = 0, w = 0            (Eqs. 2, 5)
 //   DFT        R_w = DFT2(f~ w), W = DFT2(w): in-register FFTs along the
-//              slot axis, LDS transposes between the passes, then exact
+//              slot axis with LDS transposes between the passes, or two
+//              split-bf16 matrix products on the matrix cores; then exact
 //              Hermitian symmetrisation X <- (X + conj X[-k]) / 2   (Eq. 7)
 //   loop       I times: objective w_f |R_w|^2 (Eq. 16), wave argmax with
 //              ties to the smaller bin, p = R_w[u,v] / W[0,0] (Eq. 10), model
@@ -24,21 +25,27 @@
 
 #include "fsr_device.h"
 #include "fsr_internal.h"
+#include "fsr_mfma.h"
 
 namespace fsr {
 
-constexpr int kLdsFloats = 2 * 64 * kS;   // 4096 floats = 16 KiB
-
-// Transpose scratch: two planes (re, im) of 32 x 32 floats in the lower
-// 8 KiB.  Element (r, j) lives at r * 32 + (j ^ r): rows and columns both
-// map to 32 distinct banks, so row-wise and column-wise accesses of a
-// half-wavefront are conflict-free.  The upper 8 KiB can hold one spectrum
-// in bin layout (see park()).
-__device__ __forceinline__ float* plane_re(float* lds) { return lds; }
-__device__ __forceinline__ float* plane_im(float* lds) { return lds + kS * kS; }
-__device__ __forceinline__ int pidx(int r, int j) { return r * kS + (j ^ r); }
-__device__ __forceinline__ float2* park(float* lds) {
-    return reinterpret_cast<float2*>(lds + 2 * kS * kS);
+// Reads the 2D spectrum left in the transpose planes into the bin layout,
+// (k, l) = (2s + h, c), with exact Hermitian symmetrisation
+// X[k, l] <- (X[k, l] + conj X[-k, -l]) / 2.
+__device__ __forceinline__ void planes_to_bins(float (&xr)[16], float (&xi)[16], float* lds, int lane) {
+    const int c = lane & 31, h = lane >> 5;
+    const float* pr = plane_re(lds);
+    const float* pi = plane_im(lds);
+    const int lm = (kS - c) & 31;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const int k = 2 * s + h, km = (kS - k) & 31;
+        const float ar = pr[pidx(k, c)], ai = pi[pidx(k, c)];
+        const float br = pr[pidx(km, lm)], bi = pi[pidx(km, lm)];
+        xr[s] = 0.5f * (ar + br);
+        xi[s] = 0.5f * (ai - bi);
+    }
+    wave_sync();
 }
 
 // 2D DFT of the real tile v (spatial layout) into the bin layout, exactly
@@ -73,18 +80,9 @@ __device__ __forceinline__ void dft2_real_to_bins(float (&xr)[16], float (&xi)[1
         pi[pidx(c, l + 16 * h)] = xi[l];
     }
     wave_sync();
-    // bin layout with exact Hermitian symmetrisation: (k, l) = (2s + h, c)
-    const int lm = (kS - c) & 31;
-#pragma unroll
-    for (int s = 0; s < 16; ++s) {
-        const int k = 2 * s + h, km = (kS - k) & 31;
-        const float ar = pr[pidx(k, c)], ai = pi[pidx(k, c)];
-        const float br = pr[pidx(km, lm)], bi = pi[pidx(km, lm)];
-        xr[s] = 0.5f * (ar + br);
-        xi[s] = 0.5f * (ai - bi);
-    }
-    wave_sync();
+    planes_to_bins(xr, xi, lds, lane);
 }
+
 
 // Everything a block needs to know about its image and the method.
 struct BlockJob {
@@ -98,6 +96,12 @@ struct BlockJob {
     int32_t iterations;
 };
 
+// kDft selects the forward transforms: kDftFft32 (FP32 FFTs on the vector
+// ALUs) or kDftSplitBf16 (split-bf16 products on the matrix cores).
+constexpr int kDftFft32 = 0;
+constexpr int kDftSplitBf16 = 1;
+
+template <int kDft>
 __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int L, float gamma,
                                                   const BlockTables& tab_in, float* lds) {
     // Per-block values are made opaque so that a caller looping over blocks
@@ -107,17 +111,19 @@ __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int
     BlockTables tab;
     tab.rho_pow = opaque_ptr(tab_in.rho_pow);
     tab.freq_w = opaque_ptr(tab_in.freq_w);
+    tab.mfma_dft = kDft == kDftSplitBf16 ? opaque_ptr(tab_in.mfma_dft) : nullptr;
     const int c = lane & 31, h = lane >> 5;
     const int y0 = jb.by * B - L, x0 = jb.bx * B - L;
 
-    // ---- gather and weighting (pixel (m, n) = (2s + h, c))
+    // ---- gather and weighting: pixel (m, n) = (2s + h, c), or
+    // (mfma_tile_row(s, h), c) for the matrix-core transform
     float xr[16], wr[16];   // f~ first, then (f~ - mu) w
     uint64_t any_known = 0;
     const int x = x0 + c;
     const bool xin = (unsigned)x < (unsigned)jb.width;
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
-        const int m = 2 * s + h, y = y0 + m;
+        const int m = kDft == kDftSplitBf16 ? mfma_tile_row(s, h) : 2 * s + h, y = y0 + m;
         const bool in = xin && (unsigned)y < (unsigned)jb.height;
         // out-of-image lanes load pixel 0 (always valid) and discard it
         const int64_t off = in ? (int64_t)y * jb.stride + x : 0;
@@ -157,14 +163,19 @@ __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int
 #pragma unroll
         for (int s = 0; s < 16; ++s) xr[s] = (xr[s] - mu) * wr[s];
         float xi[16], wi[16];
-        dft2_real_to_bins(xr, xi, lds, lane);
+        auto dft2 = [&](float (&re)[16], float (&im)[16]) {
+            if constexpr (kDft == kDftSplitBf16)
+                dft2_real_mfma(re, im, reinterpret_cast<const bf16x8*>(tab.mfma_dft), lane);
+            else dft2_real_to_bins(re, im, lds, lane);
+        };
+        dft2(xr, xi);
         // park the first spectrum in the upper half of the LDS while the
         // second is transformed, so both never occupy registers at once
         float2* pk = park(lds);
 #pragma unroll
         for (int s = 0; s < 16; ++s) pk[64 * s + lane] = make_float2(xr[s], xi[s]);
         wave_sync();
-        dft2_real_to_bins(wr, wi, lds, lane);
+        dft2(wr, wi);
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
             const float2 v = pk[64 * s + lane];

@@ -19,6 +19,21 @@ namespace fsr {
 
 constexpr int kSlots = 16;        // bins (or pixels) per lane
 
+// ---------------------------------------------------------------- LDS of a block
+constexpr int kLdsFloats = 2 * 64 * kS;   // 4096 floats = 16 KiB
+
+// Transpose scratch: two planes (re, im) of 32 x 32 floats in the lower
+// 8 KiB.  Element (r, j) lives at r * 32 + (j ^ r): rows and columns both
+// map to 32 distinct banks, so row-wise and column-wise accesses of a
+// half-wavefront are conflict-free.  The upper 8 KiB can hold one spectrum
+// in bin layout (see park()).
+__device__ __forceinline__ float* plane_re(float* lds) { return lds; }
+__device__ __forceinline__ float* plane_im(float* lds) { return lds + kS * kS; }
+__device__ __forceinline__ int pidx(int r, int j) { return r * kS + (j ^ r); }
+__device__ __forceinline__ float2* park(float* lds) {
+    return reinterpret_cast<float2*>(lds + 2 * kS * kS);
+}
+
 // ---------------------------------------------------------------- twiddles
 // t[q] = exp(-j 2 pi q / 32).  Built at compile time from the first octant
 // only (cos/sin series on [0, pi/4]) and the exact symmetries of the circle,

@@ -15,7 +15,13 @@ constexpr int kBins = kS * kS;    // 1024 frequency bins per block
 struct BlockTables {
     const float* rho_pow;   // [m * 32 + n]
     const float* freq_w;    // [k * 32 + l]
+    // DFT-matrix operands of the split-bf16 matrix-core transform in MFMA
+    // lane order, bf16 bit patterns [part 2][q 2][term kMfmaMaxTerms][lane 64][8]
+    const uint16_t* mfma_dft;
 };
+
+constexpr int kMfmaMaxTerms = 3;
+constexpr int kMfmaDftElems = 2 * 2 * kMfmaMaxTerms * 64 * 8;
 
 // One image of a reconstruction call.
 struct ImageDesc {
@@ -36,6 +42,7 @@ struct PlainLaunch {
     float gamma;
     BlockTables tab;
     int64_t n_blocks;
+    int32_t dft;            // 0: FP32 FFTs, 1: split-bf16 matrix products
 };
 
 hipError_t launch_plain(const PlainLaunch& p, hipStream_t stream);
@@ -64,6 +71,7 @@ struct BatchLaunch {
     int32_t block, border;
     float gamma;
     BlockTables tab;
+    int32_t dft;            // 0: FP32 FFTs, 1: split-bf16 matrix products
 };
 
 // Launches the queue reset (when chunk > 0) and the batched kernel with

@@ -1,0 +1,193 @@
+// fsr_mfma.h -- the 2D DFT of a 32 x 32 real tile as split-bf16 products on
+// the matrix cores (v_mfma_f32_32x32x16_bf16, FP32 accumulation).
+//
+// Every operand a is split into bf16 terms a_0 = bf16(a), a_1 = bf16(a - a_0)
+// (and a_2 = bf16(a - a_0 - a_1)): two terms hold a to about 2^-17 relative,
+// three to about 2^-25.  A product a b is evaluated as the sum of the terms
+// a_i b_j with i + j below the term count (3 products for two terms, 6 for
+// three), the dropped ones being of the order of the representation error.
+// The transform is two real matrix products:
+//   pass 1  C^T = X^T F            (K = m, the 32 tile rows; C = DFT along m)
+//   pass 2  Y = C F, complex, as four real products per K-step
+// with F[m][k] = exp(-j 2 pi m k / 32).  The host prepares the F operands in
+// MFMA lane order (split and permuted), so the only per-block work besides
+// the matrix instructions (36 per transform and product term) is the split
+// of X and of the pass-1 result.
+//
+// Lane layouts of v_mfma_f32_32x32x16_bf16 (lane l, h = l / 32, c = l % 32):
+//   A (32 x 16): lane l holds A[c][8 h + v], v = 0..7
+//   B (16 x 32): lane l holds B[8 h + v][c]
+//   D (32 x 32): lane l, accumulator r holds D[8 (r / 4) + 4 h + r % 4][c]
+#pragma once
+
+#include "fsr_device.h"
+
+namespace fsr {
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Spatial layout of the tile that pass 1 takes as its A operand: lane (c, h),
+// slot t = 8 q + v holds pixel (m = 16 q + 8 (v / 4) + 4 h + v % 4, n = c).
+__device__ __forceinline__ int mfma_tile_row(int t, int h) {
+    return 16 * (t >> 3) + 8 * ((t >> 2) & 1) + 4 * h + (t & 3);
+}
+
+// Number of bf16 terms each operand is split into (see the file comment).
+// Two terms (hi + lo, 3 products) leave the spectra about 2^-17 relative
+// off, which moves enough near-tied argmax decisions to miss the oracle
+// agreement bar on the concealment frame; three terms (6 products) match
+// the FP32 FFTs.
+constexpr int kTerms = 3;
+static_assert(kTerms >= 2 && kTerms <= kMfmaMaxTerms, "two or three bf16 terms per operand");
+
+// Both bf16 halves of a pair: bits of (bf16(a), bf16(b)) packed low/high.
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
+    const f32x2 v = {a, b};
+    const bf16x2 r = __builtin_convertvector(v, bf16x2);
+    return __builtin_bit_cast(uint32_t, r);
+}
+
+// Splits v[0..7] into kTerms bf16 vectors: t[0] = bf16(v), t[i] = bf16 of
+// what the earlier terms leave (the remainders are exact in FP32).
+__device__ __forceinline__ void split8(const float* v, bf16x8 (&t)[kTerms]) {
+    u32x4 w[kTerms];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        float r0 = v[2 * j], r1 = v[2 * j + 1];
+#pragma unroll
+        for (int i = 0; i < kTerms; ++i) {
+            const uint32_t p = pack_bf16(r0, r1);
+            w[i][j] = p;
+            if (i + 1 < kTerms) {
+                r0 -= __uint_as_float(p << 16);
+                r1 -= __uint_as_float(p & 0xFFFF0000u);
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < kTerms; ++i) t[i] = __builtin_bit_cast(bf16x8, w[i]);
+}
+
+__device__ __forceinline__ f32x16 mfma(const bf16x8& a, const bf16x8& b, const f32x16& c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+// acc + A B with both operands split: the products a_i b_j with
+// i + j < kTerms, smallest first.
+__device__ __forceinline__ f32x16 mfma_split(const bf16x8 (&a)[kTerms], const bf16x8 (&b)[kTerms],
+                                             f32x16 acc) {
+#pragma unroll
+    for (int order = kTerms - 1; order >= 0; --order)
+#pragma unroll
+        for (int i = 0; i <= order; ++i) acc = mfma(a[i], b[order - i], acc);
+    return acc;
+}
+
+__device__ __forceinline__ void negate(const bf16x8 (&a)[kTerms], bf16x8 (&n)[kTerms]) {
+    const u32x4 sign = {0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+#pragma unroll
+    for (int i = 0; i < kTerms; ++i) n[i] = __builtin_bit_cast(bf16x8, __builtin_bit_cast(u32x4, a[i]) ^ sign);
+}
+
+// 2D DFT of the real tile x (mfma_tile_row layout) into the bin layout
+// (lane (c, h), slot s holds bin (k = 2s + h, l = c)), exactly Hermitian.
+// Uses no LDS.  `fop` holds the host-prepared F operands,
+// [part (Re F, Im F)][q][term (kMfmaMaxTerms)][lane][8]: lane (c, h) holds entries
+// F[16 q + 8 (v / 4) + 4 h + v % 4][c], v = 0..7.  That K order is the one in
+// which pass 1 leaves C in its accumulators, and the tile rows are gathered
+// in the same order, so one operand set serves both passes.
+__device__ __forceinline__ void dft2_real_mfma(float (&xr)[16], float (&xi)[16], const bf16x8* fop_in,
+                                               int lane) {
+    const int c = lane & 31, h = lane >> 5;
+    // loaded anew by every call (they hit the cache): keeping them live
+    // from one transform to the next would cost registers
+    const bf16x8* fop = opaque_ptr(fop_in);
+    bf16x8 f[2][2][kTerms];
+#pragma unroll
+    for (int part = 0; part < 2; ++part)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int i = 0; i < kTerms; ++i)
+                f[part][q][i] = fop[((part * 2 + q) * kMfmaMaxTerms + i) * 64 + lane];
+    bf16x8 x[2][kTerms];
+    split8(xr, x[0]);
+    split8(xr + 8, x[1]);
+
+    // pass 1: C_part^T[n][k] = sum_m x[m][n] F_part[m][k]; accumulator r of
+    // lane (c, h) holds C_part[k = c][n = 8 (r / 4) + 4 h + r % 4]
+    f32x16 cp[2];
+#pragma unroll
+    for (int part = 0; part < 2; ++part) {
+        f32x16 acc = {};
+#pragma unroll
+        for (int q = 0; q < 2; ++q) acc = mfma_split(x[q], f[part][q], acc);
+        cp[part] = acc;
+    }
+
+    // pass 2: accumulators 8 q .. 8 q + 7 are the A operand of K-step q:
+    // Y_re = C_re Re F - C_im Im F,  Y_im = C_re Im F + C_im Re F
+    bf16x8 a[2][2][kTerms];
+#pragma unroll
+    for (int part = 0; part < 2; ++part)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            float v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = cp[part][8 * q + j];
+            split8(v, a[part][q]);
+        }
+    f32x16 yr = {}, yi = {};
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        bf16x8 na[kTerms];
+        negate(a[1][q], na);
+        yr = mfma_split(a[0][q], f[0][q], yr);
+        yi = mfma_split(a[0][q], f[1][q], yi);
+        yr = mfma_split(na, f[1][q], yr);
+        yi = mfma_split(a[1][q], f[0][q], yi);
+    }
+
+    // accumulator r = 4 g + i of lane (c, h) holds Y[k = 8 g + 4 h + i][l = c].
+    // Swapping the upper half of accumulator 4 g + i with the lower half of
+    // 4 g + i + 1 (i even) leaves bins k = 8 g + i + h in the first and
+    // k = 8 g + 4 + i + h in the second: slots 4 g + i / 2 and 4 g + 2 + i / 2.
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int i = 0; i < 4; i += 2) {
+            const auto re = __builtin_amdgcn_permlane32_swap(__float_as_uint(yr[4 * g + i]),
+                                                             __float_as_uint(yr[4 * g + i + 1]), false, false);
+            const auto im = __builtin_amdgcn_permlane32_swap(__float_as_uint(yi[4 * g + i]),
+                                                             __float_as_uint(yi[4 * g + i + 1]), false, false);
+            xr[4 * g + i / 2] = __uint_as_float(re[0]);
+            xi[4 * g + i / 2] = __uint_as_float(im[0]);
+            xr[4 * g + 2 + i / 2] = __uint_as_float(re[1]);
+            xi[4 * g + 2 + i / 2] = __uint_as_float(im[1]);
+        }
+
+    // exact Hermitian symmetrisation X <- (X + conj X[-k, -l]) / 2: bin
+    // (2s + h, c) pairs with lane ((32 - c) mod 32) + 32 h, slot (16 - s) mod 16
+    // when h = 0 and 15 - s when h = 1; rotating the slots of the upper half by
+    // one makes the partner slot (16 - s) mod 16 in both halves.
+    const int paddr = 4 * (((kS - c) & 31) + 32 * h);
+    float tr[16], ti[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        tr[t] = h ? xr[(t + 15) & 15] : xr[t];
+        ti[t] = h ? xi[(t + 15) & 15] : xi[t];
+    }
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const float br = __int_as_float(__builtin_amdgcn_ds_bpermute(paddr, __float_as_int(tr[(16 - s) & 15])));
+        const float bi = __int_as_float(__builtin_amdgcn_ds_bpermute(paddr, __float_as_int(ti[(16 - s) & 15])));
+        xr[s] = 0.5f * (xr[s] + br);
+        xi[s] = 0.5f * (xi[s] - bi);
+    }
+}
+
+}  // namespace fsr

@@ -3,6 +3,7 @@
 
 namespace fsr {
 
+template <int kDft>
 __global__ __launch_bounds__(64) void fsr_plain_s32(PlainLaunch p) {
     __shared__ float lds[kLdsFloats];
     const int64_t blk = xcd_contiguous(blockIdx.x, p.n_blocks);
@@ -18,12 +19,15 @@ __global__ __launch_bounds__(64) void fsr_plain_s32(PlainLaunch p) {
     jb.by = (int32_t)(blk / im.nbx);
     jb.bx = (int32_t)(blk % im.nbx);
     jb.iterations = im.iterations;
-    reconstruct_block(jb, p.block, p.border, p.gamma, p.tab, lds);
+    reconstruct_block<kDft>(jb, p.block, p.border, p.gamma, p.tab, lds);
 }
 
 hipError_t launch_plain(const PlainLaunch& p, hipStream_t stream) {
     if (p.n_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(fsr_plain_s32, dim3((unsigned)p.n_blocks), dim3(64), 0, stream, p);
+    if (p.dft == kDftSplitBf16)
+        hipLaunchKernelGGL(fsr_plain_s32<kDftSplitBf16>, dim3((unsigned)p.n_blocks), dim3(64), 0, stream, p);
+    else
+        hipLaunchKernelGGL(fsr_plain_s32<kDftFft32>, dim3((unsigned)p.n_blocks), dim3(64), 0, stream, p);
     return hipGetLastError();
 }
 

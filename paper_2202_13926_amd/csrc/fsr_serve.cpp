@@ -404,8 +404,6 @@ fsr_status fsr_server_create(fsr_context* ctx, const fsr_params* params, const f
     fsr_status st = validate_params(params);
     if (st != FSR_OK) return st;
     if ((st = check_supported(params)) != FSR_OK) return st;
-    if (params->dft != FSR_DFT_FP32)
-        return errorf(FSR_ERR_UNSUPPORTED, "the server runs the FP32 DFT");
     if ((st = check_config(cfg)) != FSR_OK) return st;
     fsr_server* s = new (std::nothrow) fsr_server();
     if (!s) return errorf(FSR_ERR_OUT_OF_MEMORY, "server allocation failed");
