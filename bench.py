@@ -163,6 +163,40 @@ def bench_precision(ctx, steps: int = 3):
     return res
 
 
+def bench_argmax_ablation(ctx, img32, mask, params, steps: int = 5):
+    """The paper's comparison (Sec. IV): the same frame and parameters with
+    the argmax reduced through an LDS tree instead of in registers."""
+    import torch
+
+    import paper_2202_13926_amd as fsr
+
+    dev = torch.device("cuda:0")
+    ti = torch.from_numpy(img32).to(dev)
+    tm = torch.from_numpy(mask).to(dev)
+    o = torch.empty_like(ti)
+    stream = torch.cuda.current_stream(dev)
+    variants = {tag: fsr.make_params(block=params.block, border=params.border,
+                                     iterations=params.iterations, rho=params.rho,
+                                     gamma=params.gamma, flags=flags)
+                for tag, flags in (("register_argmax", 0), ("lds_argmax", fsr.FSR_FLAG_LDS_ARGMAX))}
+    best = {}
+    for _ in range(2):                     # alternate the variants; keep each one's best
+        for tag, p in variants.items():
+            fsr.fsr_reconstruct(ctx, ti, tm, o, p, None, stream)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
+                fsr.fsr_reconstruct(ctx, ti, tm, o, p, None, stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            best[tag] = min(best.get(tag, 1e30), e0.elapsed_time(e1) / steps)
+    res = {tag: {"ms": round(ms, 4), "mpx_s": round(img32.size / ms / 1e3, 2)}
+           for tag, ms in best.items()}
+    res["speedup_register_over_lds"] = round(res["lds_argmax"]["ms"] / res["register_argmax"]["ms"], 3)
+    return res
+
+
 def bench_batched(ctx, steps: int = 5):
     """64 uneven images (256x256 .. 1920x1080, quarter or 10-50 % uniform loss,
     I in {50, 100, 200}) with split-bf16 DFTs and FP32 iterations: the tuned
@@ -395,6 +429,7 @@ def main():
                      "avg_launch_ms": round(ms_per_step, 5),
                      "traffic": measured_traffic()},
     }
+    res["argmax_ablation"] = bench_argmax_ablation(ctx, img32, mask, params)
     if not args.no_batched:
         res["batched"] = bench_batched(ctx)
     if not args.no_precision:

@@ -65,11 +65,23 @@ enum {
     FSR_DFT_SPLIT_BF16 = 1   /* split-bf16 DFT-matrix products on MFMA     */
 };
 
+/* Flags of fsr_params.flags. */
+enum {
+    /* Reduce the argmax of Eq. 8 through a shared-memory (LDS) tree over
+     * all S^2 (objective, bin) pairs instead of in registers across the
+     * wavefront: the scheme Sec. IV compares the register-based argmax
+     * against.  Same choices, hence bitwise the same output; slower.  For
+     * fsr_reconstruct with FSR_DFT_FP32 only (FSR_ERR_UNSUPPORTED
+     * elsewhere). */
+    FSR_FLAG_LDS_ARGMAX = 1u
+};
+
 /*
  * Method parameters (Sec. II; the paper's defaults B = 4, rho = 0.7,
  * gamma = 0.5 are Sec. IV's).  Validated before any launch:
  *   block >= 1, border >= 0, S = block + 2*border even and <= 32,
- *   iterations >= 0, 0 < rho <= 1, 0 < gamma <= 1 (Sec. II), flags == 0.
+ *   iterations >= 0, 0 < rho <= 1, 0 < gamma <= 1 (Sec. II), flags a
+ *   combination of FSR_FLAG_*.
  * This build runs S = 32 with block <= 8 (FSR_ERR_UNSUPPORTED otherwise).
  */
 typedef struct fsr_params {
@@ -79,7 +91,7 @@ typedef struct fsr_params {
     float rho;           /* spatial decay factor of the weight, Eq. 5       */
     float gamma;         /* orthogonality deficiency compensation, Eq. 11   */
     int32_t dft;         /* FSR_DFT_*                                       */
-    uint32_t flags;      /* reserved, must be 0                             */
+    uint32_t flags;      /* FSR_FLAG_* bits                                 */
 } fsr_params;
 
 typedef struct fsr_context fsr_context;

@@ -5,7 +5,7 @@ ABI of include/fsr.h (libfsr.so, built in-tree); this package is its thin
 Python binding.  See :mod:`paper_2202_13926_amd.binding`.
 """
 from .binding import (  # noqa: F401
-    FSR_DFT_FP32, FSR_DFT_SPLIT_BF16, BatchGraph, BatchItem, Context, FsrError, Workspace,
+    FSR_DFT_FP32, FSR_DFT_SPLIT_BF16, FSR_FLAG_LDS_ARGMAX, BatchGraph, BatchItem, Context, FsrError, Workspace,
     declared_functions, fsr_batch_autotune, fsr_batch_schedule, fsr_batched_workspace_size,
     fsr_context_create, fsr_context_destroy, fsr_image_desc, fsr_num_blocks, fsr_params,
     fsr_params_default, fsr_params_validate, fsr_reconstruct, fsr_reconstruct_batched, fsr_version,

@@ -27,6 +27,8 @@ FSR_ERR_NOT_READY = 7
 FSR_DFT_FP32 = 0
 FSR_DFT_SPLIT_BF16 = 1
 
+FSR_FLAG_LDS_ARGMAX = 1
+
 
 class FsrError(RuntimeError):
     def __init__(self, status: int, message: str):

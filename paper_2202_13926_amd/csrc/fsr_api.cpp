@@ -83,7 +83,8 @@ fsr_status validate_params(const fsr_params* p) {
         return fail(FSR_ERR_INVALID_ARG, "gamma must lie in (0, 1] (got %g)", (double)p->gamma);
     if (p->dft != FSR_DFT_FP32 && p->dft != FSR_DFT_SPLIT_BF16)
         return fail(FSR_ERR_INVALID_ARG, "unknown dft mode %d", p->dft);
-    if (p->flags != 0) return fail(FSR_ERR_INVALID_ARG, "flags must be 0 (got 0x%x)", p->flags);
+    if ((p->flags & ~(uint32_t)FSR_FLAG_LDS_ARGMAX) != 0)
+        return fail(FSR_ERR_INVALID_ARG, "unknown flags 0x%x", p->flags);
     return FSR_OK;
 }
 
@@ -347,6 +348,9 @@ fsr_status fsr_reconstruct(fsr_context* ctx, const float* image, const uint8_t* 
     if ((st = validate_image(image, mask, out, height, width, stride, params->block)) != FSR_OK)
         return st;
 
+    if ((params->flags & FSR_FLAG_LDS_ARGMAX) && params->dft != FSR_DFT_FP32)
+        return fail(FSR_ERR_UNSUPPORTED, "the LDS argmax runs with FSR_DFT_FP32 only");
+
     DeviceGuard g(ctx->device);
     if (g.error() != hipSuccess) return hip_fail(g.error(), "hipSetDevice");
     PlainLaunch p{};
@@ -366,6 +370,7 @@ fsr_status fsr_reconstruct(fsr_context* ctx, const float* image, const uint8_t* 
     p.gamma = params->gamma;
     p.n_blocks = fsr_num_blocks(height, width, params->block);
     p.dft = params->dft == FSR_DFT_SPLIT_BF16 ? 1 : 0;
+    p.lds_argmax = (params->flags & FSR_FLAG_LDS_ARGMAX) ? 1 : 0;
     hipError_t e = launch_plain(p, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "launch of the reconstruction kernel");
     return FSR_OK;

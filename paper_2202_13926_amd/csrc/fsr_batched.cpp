@@ -120,6 +120,8 @@ fsr_status prepare(fsr_context* ctx, const fsr_image_desc* descs, int32_t n, con
     fsr_status st = validate_params(params);
     if (st != FSR_OK) return st;
     if ((st = check_supported(params)) != FSR_OK) return st;
+    if (params->flags & FSR_FLAG_LDS_ARGMAX)
+        return errorf(FSR_ERR_UNSUPPORTED, "the LDS argmax runs in fsr_reconstruct only");
     if ((st = check_schedule(schedule)) != FSR_OK) return st;
     if ((st = plan_batch(descs, n, params, plan)) != FSR_OK) return st;
     if (!workspace && n > 0) return errorf(FSR_ERR_INVALID_ARG, "workspace is NULL");

@@ -101,9 +101,24 @@ struct BlockJob {
 constexpr int kDftFft32 = 0;
 constexpr int kDftSplitBf16 = 1;
 
-template <int kDft>
+// kArgmax selects the cross-bin reduction of the argmax: kArgmaxWave (each
+// lane's 16 keys combined in registers, then DPP steps across the wavefront)
+// or kArgmaxLds, the shared-memory scheme the paper compares against: all
+// 1024 (key, bin) pairs are written to LDS and halved in a tree of ten
+// LDS rounds.  Both pick the same bin (largest key, then smallest bin).
+constexpr int kArgmaxWave = 0;
+constexpr int kArgmaxLds = 1;
+constexpr int kArgmaxLdsFloats = 2 * kBins;   // (key, bin) pairs, 8 KiB
+
+// Pair order of the LDS tree: larger key, then smaller bin.
+__device__ __forceinline__ uint2 better_pair(uint2 a, uint2 b) {
+    return (b.x > a.x || (b.x == a.x && b.y < a.y)) ? b : a;
+}
+
+template <int kDft, int kArgmax = kArgmaxWave>
 __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int L, float gamma,
-                                                  const BlockTables& tab_in, float* lds) {
+                                                  const BlockTables& tab_in, float* lds,
+                                                  uint2* argmax_lds = nullptr) {
     // Per-block values are made opaque so that a caller looping over blocks
     // (the persistent kernel) does not hoist the table loads and lane
     // constants out of its loop and keep them live across every block.
@@ -214,17 +229,46 @@ __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int
             // order) with the 4 lowest mantissa bits replaced by 15 - slot.
             // Objectives that agree to 2^-19 relative tie, and ties go to the
             // smaller slot, then (below) to the lower lane: the smaller bin.
-            uint32_t lmax = 0;
+            int idx;
+            if constexpr (kArgmax == kArgmaxWave) {
+                uint32_t lmax = 0;
 #pragma unroll
-            for (int s = 0; s < 16; ++s) {
-                const float e = fmaf(xr[s], xr[s], xi[s] * xi[s]);
-                const uint32_t key = (__float_as_uint(e * wf[s]) & 0xFFFFFFF0u) | (uint32_t)(15 - s);
-                lmax = umax(lmax, key);
+                for (int s = 0; s < 16; ++s) {
+                    const float e = fmaf(xr[s], xr[s], xi[s] * xi[s]);
+                    const uint32_t key = (__float_as_uint(e * wf[s]) & 0xFFFFFFF0u) | (uint32_t)(15 - s);
+                    lmax = umax(lmax, key);
+                }
+                const uint32_t mx = wave_max_u32(lmax);
+                const int ln = (int)__builtin_ctzll(ballot(lmax == mx));
+                idx = 64 * (15 - (int)(mx & 15u)) + ln;
+            } else {
+#pragma unroll
+                for (int s = 0; s < 16; ++s) {
+                    const float e = fmaf(xr[s], xr[s], xi[s] * xi[s]);
+                    const uint32_t key = (__float_as_uint(e * wf[s]) & 0xFFFFFFF0u) | (uint32_t)(15 - s);
+                    argmax_lds[64 * s + lane] = make_uint2(key, (uint32_t)(64 * s + lane));
+                }
+                wave_sync();
+                // halve 1024 -> 64 entries, each lane owning entries lane + 64 j
+#pragma unroll
+                for (int half = kBins / 2; half >= 64; half >>= 1) {
+#pragma unroll
+                    for (int j = 0; j < half / 64; ++j) {
+                        const int e = lane + 64 * j;
+                        argmax_lds[e] = better_pair(argmax_lds[e], argmax_lds[e + half]);
+                    }
+                    wave_sync();
+                }
+                // 64 -> 1 with a shrinking set of lanes
+#pragma unroll
+                for (int half = 32; half >= 1; half >>= 1) {
+                    if (lane < half) argmax_lds[lane] = better_pair(argmax_lds[lane], argmax_lds[lane + half]);
+                    wave_sync();
+                }
+                idx = __builtin_amdgcn_readfirstlane((int)argmax_lds[0].y);
+                wave_sync();   // the next iteration overwrites the pairs
             }
-            const uint32_t mx = wave_max_u32(lmax);
-            const int ln = (int)__builtin_ctzll(ballot(lmax == mx));
-            const int slot = 15 - (int)(mx & 15u);
-            const int idx = 64 * slot + ln;
+            const int slot = idx >> 6, ln = idx & 63;
             const float pr = readlane_f(xr[slot], ln);
             const float pim = readlane_f(xi[slot], ln);
             const int u = idx >> 5, v = idx & 31;

@@ -43,6 +43,7 @@ struct PlainLaunch {
     BlockTables tab;
     int64_t n_blocks;
     int32_t dft;            // 0: FP32 FFTs, 1: split-bf16 matrix products
+    int32_t lds_argmax;     // 1: argmax reduced through an LDS tree (FP32 FFTs only)
 };
 
 hipError_t launch_plain(const PlainLaunch& p, hipStream_t stream);

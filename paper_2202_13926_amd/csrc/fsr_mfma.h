@@ -72,6 +72,11 @@ __device__ __forceinline__ void split8(const float* v, bf16x8 (&t)[kTerms]) {
     for (int i = 0; i < kTerms; ++i) t[i] = __builtin_bit_cast(bf16x8, w[i]);
 }
 
+// (a where mask bits are set, b elsewhere): one v_bfi_b32.
+__device__ __forceinline__ float blend(uint32_t mask, float a, float b) {
+    return __uint_as_float((mask & __float_as_uint(a)) | (~mask & __float_as_uint(b)));
+}
+
 __device__ __forceinline__ f32x16 mfma(const bf16x8& a, const bf16x8& b, const f32x16& c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
@@ -174,12 +179,17 @@ __device__ __forceinline__ void dft2_real_mfma(float (&xr)[16], float (&xi)[16],
     // (2s + h, c) pairs with lane ((32 - c) mod 32) + 32 h, slot (16 - s) mod 16
     // when h = 0 and 15 - s when h = 1; rotating the slots of the upper half by
     // one makes the partner slot (16 - s) mod 16 in both halves.
+    // The per-lane choice is a bit blend under an opaque all-ones / all-zeros
+    // mask: written as a select, the compiler turns the pair of neighbouring
+    // registers into a dynamically indexed register and expands it into a
+    // 16-way select chain.
     const int paddr = 4 * (((kS - c) & 31) + 32 * h);
+    const uint32_t upper = (uint32_t)opaque(-h);
     float tr[16], ti[16];
 #pragma unroll
     for (int t = 0; t < 16; ++t) {
-        tr[t] = h ? xr[(t + 15) & 15] : xr[t];
-        ti[t] = h ? xi[(t + 15) & 15] : xi[t];
+        tr[t] = blend(upper, xr[(t + 15) & 15], xr[t]);
+        ti[t] = blend(upper, xi[(t + 15) & 15], xi[t]);
     }
 #pragma unroll
     for (int s = 0; s < 16; ++s) {

@@ -3,9 +3,9 @@
 
 namespace fsr {
 
-template <int kDft>
+template <int kDft, int kArgmax>
 __global__ __launch_bounds__(64) void fsr_plain_s32(PlainLaunch p) {
-    __shared__ float lds[kLdsFloats];
+    __shared__ __align__(16) float lds[kLdsFloats + (kArgmax == kArgmaxLds ? kArgmaxLdsFloats : 0)];
     const int64_t blk = xcd_contiguous(blockIdx.x, p.n_blocks);
     const ImageDesc& im = p.img;
     BlockJob jb;
@@ -19,15 +19,21 @@ __global__ __launch_bounds__(64) void fsr_plain_s32(PlainLaunch p) {
     jb.by = (int32_t)(blk / im.nbx);
     jb.bx = (int32_t)(blk % im.nbx);
     jb.iterations = im.iterations;
-    reconstruct_block<kDft>(jb, p.block, p.border, p.gamma, p.tab, lds);
+    reconstruct_block<kDft, kArgmax>(jb, p.block, p.border, p.gamma, p.tab, lds,
+                                     reinterpret_cast<uint2*>(lds + kLdsFloats));
 }
 
 hipError_t launch_plain(const PlainLaunch& p, hipStream_t stream) {
     if (p.n_blocks <= 0) return hipSuccess;
-    if (p.dft == kDftSplitBf16)
-        hipLaunchKernelGGL(fsr_plain_s32<kDftSplitBf16>, dim3((unsigned)p.n_blocks), dim3(64), 0, stream, p);
-    else
-        hipLaunchKernelGGL(fsr_plain_s32<kDftFft32>, dim3((unsigned)p.n_blocks), dim3(64), 0, stream, p);
+    const dim3 grid((unsigned)p.n_blocks), block(64);
+    if (p.lds_argmax) {
+        if (p.dft != kDftFft32) return hipErrorInvalidValue;   // rejected by the host API first
+        hipLaunchKernelGGL((fsr_plain_s32<kDftFft32, kArgmaxLds>), grid, block, 0, stream, p);
+    } else if (p.dft == kDftSplitBf16) {
+        hipLaunchKernelGGL((fsr_plain_s32<kDftSplitBf16, kArgmaxWave>), grid, block, 0, stream, p);
+    } else {
+        hipLaunchKernelGGL((fsr_plain_s32<kDftFft32, kArgmaxWave>), grid, block, 0, stream, p);
+    }
     return hipGetLastError();
 }
 

@@ -404,6 +404,8 @@ fsr_status fsr_server_create(fsr_context* ctx, const fsr_params* params, const f
     fsr_status st = validate_params(params);
     if (st != FSR_OK) return st;
     if ((st = check_supported(params)) != FSR_OK) return st;
+    if (params->flags & FSR_FLAG_LDS_ARGMAX)
+        return errorf(FSR_ERR_UNSUPPORTED, "the LDS argmax runs in fsr_reconstruct only");
     if ((st = check_config(cfg)) != FSR_OK) return st;
     fsr_server* s = new (std::nothrow) fsr_server();
     if (!s) return errorf(FSR_ERR_OUT_OF_MEMORY, "server allocation failed");

@@ -36,7 +36,7 @@ def test_defaults_and_block_count(lib):
 @pytest.mark.parametrize("kw", [
     dict(block=0), dict(border=-1), dict(block=3), dict(block=4, border=15),
     dict(iterations=-1), dict(rho=0.0), dict(rho=1.5), dict(gamma=0.0), dict(gamma=1.01),
-    dict(rho=float("nan")), dict(dft=7), dict(flags=1),
+    dict(rho=float("nan")), dict(dft=7), dict(flags=2), dict(flags=0x80000001),
 ])
 def test_invalid_params_rejected(lib, kw):
     with pytest.raises(fsr.FsrError) as e:
@@ -47,7 +47,8 @@ def test_invalid_params_rejected(lib, kw):
 
 def test_valid_params_accepted():
     for kw in (dict(), dict(block=2, border=15), dict(block=8, border=12, iterations=0),
-               dict(rho=1.0, gamma=1.0), dict(block=4, border=6)):
+               dict(rho=1.0, gamma=1.0), dict(block=4, border=6),
+               dict(flags=fsr.FSR_FLAG_LDS_ARGMAX), dict(dft=fsr.FSR_DFT_SPLIT_BF16)):
         fsr.fsr_params_validate(fsr.make_params(**kw))
 
 
@@ -71,6 +72,9 @@ def test_reconstruct_validates_before_touching_the_device(lib):
     p16 = fsr.make_params(block=4, border=6)
     assert _call(lib, fake_ctx, img, msk, out, 8, 8, 8, p16) == binding.FSR_ERR_UNSUPPORTED
     assert _call(lib, fake_ctx, img, msk, out, 8, 8, 8, fsr.make_params(block=12, border=10)) == binding.FSR_ERR_UNSUPPORTED
+    # the LDS-argmax ablation runs with the FP32 FFTs only
+    lds_bf16 = fsr.make_params(flags=fsr.FSR_FLAG_LDS_ARGMAX, dft=fsr.FSR_DFT_SPLIT_BF16)
+    assert _call(lib, fake_ctx, img, msk, out, 8, 8, 8, lds_bf16) == binding.FSR_ERR_UNSUPPORTED
 
 
 def test_missing_library_fails_loudly(tmp_path):
@@ -112,6 +116,7 @@ def test_batched_validates_before_touching_the_device(lib):
               binding.fsr_batch_schedule(1, 0, 10, 7)):
         assert call([good], 1, sched=s) == E
     assert call([good], 1, params=fsr.make_params(block=4, border=6)) == binding.FSR_ERR_UNSUPPORTED
+    assert call([good], 1, params=fsr.make_params(flags=fsr.FSR_FLAG_LDS_ARGMAX)) == binding.FSR_ERR_UNSUPPORTED
     assert lib.fsr_last_error_message().decode()
     out = ctypes.c_void_p()
     arr = (binding.fsr_image_desc * 1)(good)
@@ -137,6 +142,8 @@ def test_server_config_validated_before_touching_the_device(lib):
     c = binding.make_server_config()
     assert lib.fsr_server_create(None, ctypes.byref(p), ctypes.byref(c), ctypes.byref(out)) == E
     assert lib.fsr_server_create(fake_ctx, ctypes.byref(fsr.make_params(block=4, border=6)),
+                                 ctypes.byref(c), ctypes.byref(out)) == binding.FSR_ERR_UNSUPPORTED
+    assert lib.fsr_server_create(fake_ctx, ctypes.byref(fsr.make_params(flags=fsr.FSR_FLAG_LDS_ARGMAX)),
                                  ctypes.byref(c), ctypes.byref(out)) == binding.FSR_ERR_UNSUPPORTED
     t = ctypes.c_uint64()
     req = binding.fsr_request(0x1000, 0x2000, 8, 8, 8, 10, 0)

@@ -1,0 +1,72 @@
+"""The shared-memory (LDS) argmax against the register argmax (Sec. IV).
+
+Both reductions order the (objective key, bin) pairs the same way, largest
+key first and the smaller bin on equal keys, so a frame reconstructed with
+FSR_FLAG_LDS_ARGMAX must be bitwise identical, output and argmax log, to one
+reconstructed with the default wavefront reduction; the oracle pins the
+LDS variant independently on the small frame.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth.metrics import parity_report
+
+torch = pytest.importorskip("torch")
+import paper_2202_13926_amd as fsr  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return fsr.Context(0)
+
+
+def run(ctx, img, mask, params):
+    ti = torch.from_numpy(np.ascontiguousarray(img, np.float32)).to(DEV)
+    tm = torch.from_numpy(np.ascontiguousarray(mask, np.uint8)).to(DEV)
+    out, lg = fsr.reconstruct(ti, tm, params, ctx=ctx, log=True)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), lg.cpu().numpy().view(np.uint16)[:, :params.iterations]
+
+
+def test_lds_argmax_small64_against_oracle(ctx):
+    print("\n[gpu case] LDS argmax: small64 vs the FP64 oracle", flush=True)
+    w = synth.workload("small64")
+    img, mask = w.inputs()
+    img32 = img.astype(np.float32)
+    g, gl = run(ctx, img32, mask, fsr.make_params(flags=fsr.FSR_FLAG_LDS_ARGMAX))
+    o, ol, _ = oracle.reconstruct(img32.astype(np.float64), mask, w.iterations, log=True,
+                                  decision=oracle.DECISION_KERNEL)
+    rep = parity_report(img32, mask, g, o, gl, ol)
+    print(f"[parity] small64 lds-argmax: {rep}", flush=True)
+    assert rep["known_bitwise"] and rep["frac_le_1"] >= 0.999 and rep["psnr_gap"] <= 0.05
+    assert rep["argmax_agree"] == 1.0
+
+
+@pytest.mark.parametrize("name,iters", [("small64", 100), ("fhd_quarter", 100), ("uhd_concealment", 20)])
+def test_lds_argmax_equals_register_argmax(ctx, name, iters):
+    print(f"\n[gpu case] LDS argmax vs register argmax, {name} I={iters}, bitwise", flush=True)
+    img, mask = synth.workload(name).inputs()
+    a, la = run(ctx, img, mask, fsr.make_params(iterations=iters))
+    b, lb = run(ctx, img, mask, fsr.make_params(iterations=iters, flags=fsr.FSR_FLAG_LDS_ARGMAX))
+    assert np.array_equal(la, lb)
+    assert np.array_equal(a, b)
+
+
+def test_lds_argmax_edge_cases(ctx):
+    print("\n[gpu case] LDS argmax: empty supports, I = 0, ragged 37x50", flush=True)
+    img, mask = synth.make_image(96, 96, 9), synth.quarter_mask(96, 96, 10)
+    mask[8:88, 8:88] = 0
+    for it in (0, 25):
+        a, la = run(ctx, img, mask, fsr.make_params(iterations=it))
+        b, lb = run(ctx, img, mask, fsr.make_params(iterations=it, flags=fsr.FSR_FLAG_LDS_ARGMAX))
+        assert np.array_equal(a, b) and np.array_equal(la, lb)
+    img, mask = synth.make_image(37, 50, 41), synth.quarter_mask(37, 50, 42)
+    a, la = run(ctx, img, mask, fsr.make_params(iterations=60))
+    b, lb = run(ctx, img, mask, fsr.make_params(iterations=60, flags=fsr.FSR_FLAG_LDS_ARGMAX))
+    assert np.array_equal(a, b) and np.array_equal(la, lb)
