@@ -37,7 +37,8 @@ def algorithmic_flops_per_block(S: int, B: int, iters: int) -> float:
 
 
 KERNEL_SOURCES = ("paper_2202_13926_amd/csrc/fsr_block.h", "paper_2202_13926_amd/csrc/fsr_device.h",
-                  "paper_2202_13926_amd/csrc/fsr_plain.hip", "paper_2202_13926_amd/csrc/fsr_internal.h")
+                  "paper_2202_13926_amd/csrc/fsr_mfma.h", "paper_2202_13926_amd/csrc/fsr_plain.hip",
+                  "paper_2202_13926_amd/csrc/fsr_internal.h", "paper_2202_13926_amd/build.py")
 PMC_SUMMARY = "profiles/fsr_plain_s32_fhd_quarter_pmc.md"
 
 
