@@ -198,6 +198,46 @@ def bench_argmax_ablation(ctx, img32, mask, params, steps: int = 5):
     return res
 
 
+def bench_multiresolution(ctx, steps: int = 5):
+    """Frame rates at S = 16 (B = 4, L = 6), I = 100, quarter-sampling masks,
+    for the paper's real-time table resolutions (Sec. IV: VGA, SVGA, FHD,
+    UHD), plus the 1080p frame at every support size this build runs."""
+    import torch
+
+    import paper_2202_13926_amd as fsr
+    import synth
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+
+    def frame_ms(h, w, B, L, seed):
+        img = synth.make_image(h, w, seed).astype(np.float32)
+        mask = synth.quarter_mask(h, w, seed + 1)
+        ti = torch.from_numpy(img).to(dev)
+        tm = torch.from_numpy(mask).to(dev)
+        o = torch.empty_like(ti)
+        p = fsr.make_params(block=B, border=L, iterations=100)
+        fsr.fsr_reconstruct(ctx, ti, tm, o, p, None, stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            fsr.fsr_reconstruct(ctx, ti, tm, o, p, None, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    res = {"workload": "synthetic frames, quarter-sampling masks, I=100, rho=0.7, gamma=0.5",
+           "s16_fps": {}, "fhd_ms_by_support": {}}
+    for name, (h, w) in (("VGA 640x480", (480, 640)), ("SVGA 800x600", (600, 800)),
+                         ("FHD 1920x1080", (1080, 1920)), ("UHD 3840x2160", (2160, 3840))):
+        ms = frame_ms(h, w, 4, 6, 1700)
+        res["s16_fps"][name] = round(1e3 / ms, 2)
+    for S in (8, 16, 24, 32):
+        res["fhd_ms_by_support"][f"S={S}"] = round(frame_ms(1080, 1920, 4, (S - 4) // 2, 1800), 4)
+    return res
+
+
 def bench_batched(ctx, steps: int = 5):
     """64 uneven images (256x256 .. 1920x1080, quarter or 10-50 % uniform loss,
     I in {50, 100, 200}) with split-bf16 DFTs and FP32 iterations: the tuned
@@ -431,6 +471,7 @@ def main():
                      "traffic": measured_traffic()},
     }
     res["argmax_ablation"] = bench_argmax_ablation(ctx, img32, mask, params)
+    res["multiresolution"] = bench_multiresolution(ctx)
     if not args.no_batched:
         res["batched"] = bench_batched(ctx)
     if not args.no_precision:

@@ -90,7 +90,8 @@ fsr_status validate_params(const fsr_params* p) {
 
 fsr_status check_supported(const fsr_params* p) {
     const int S = p->block + 2 * p->border;
-    if (S != kS) return fail(FSR_ERR_UNSUPPORTED, "this build runs support size 32 only (got %d)", S);
+    if (S != 8 && S != 16 && S != 24 && S != kS)
+        return fail(FSR_ERR_UNSUPPORTED, "this build runs support sizes 8, 16, 24 and 32 (got %d)", S);
     if (p->block > 8) return fail(FSR_ERR_UNSUPPORTED, "this build runs block <= 8 (got %d)", p->block);
     return FSR_OK;
 }
@@ -122,25 +123,53 @@ fsr_status validate_image(const float* image, const uint8_t* mask, const float* 
 // Spatial weight rho^dist from the support centre (S-1)/2 (Eq. 5, before
 // masking) and frequency weight w_f (Eq. 9), evaluated in double and rounded
 // once to float.
-static std::vector<float> host_rho_pow(float rho) {
-    std::vector<float> t(kBins);
-    const double c = 0.5 * (kS - 1);
-    for (int m = 0; m < kS; ++m)
-        for (int n = 0; n < kS; ++n) {
+static std::vector<float> host_rho_pow(int S, float rho) {
+    std::vector<float> t((size_t)S * S);
+    const double c = 0.5 * (S - 1);
+    for (int m = 0; m < S; ++m)
+        for (int n = 0; n < S; ++n) {
             const double d = std::sqrt((m - c) * (m - c) + (n - c) * (n - c));
-            t[m * kS + n] = (float)std::pow((double)rho, d);
+            t[(size_t)m * S + n] = (float)std::pow((double)rho, d);
         }
     return t;
 }
 
-static std::vector<float> host_freq_w() {
-    std::vector<float> t(kBins);
-    const double half = 0.5 * kS;
-    for (int k = 0; k < kS; ++k)
-        for (int l = 0; l < kS; ++l) {
+static std::vector<float> host_freq_w(int S) {
+    std::vector<float> t((size_t)S * S);
+    const double half = 0.5 * S;
+    for (int k = 0; k < S; ++k)
+        for (int l = 0; l < S; ++l) {
             const double kt = half - std::fabs(k - half), lt = half - std::fabs(l - half);
-            const double a = 1.0 - std::sqrt(2.0) * std::sqrt((kt * kt + lt * lt) / (double)(kS * kS));
-            t[k * kS + l] = (float)(a * a);
+            const double a = 1.0 - std::sqrt(2.0) * std::sqrt((kt * kt + lt * lt) / (double)(S * S));
+            t[(size_t)k * S + l] = (float)(a * a);
+        }
+    return t;
+}
+
+// DFT table of the smaller supports: F[m][k] = exp(-j 2 pi m k / S) as float2,
+// from twiddles t[q] = exp(-j 2 pi q / S) computed on [0, pi] and mirrored,
+// so that t[S - q] is exactly conj(t[q]) and t[0], t[S/4], t[S/2] are exact.
+static std::vector<float> host_dft_sg(int S) {
+    const double pi = 3.14159265358979323846;
+    std::vector<double> tr(S), ti(S);
+    for (int q = 0; 2 * q <= S; ++q) {
+        double c = std::cos(2.0 * pi * q / S), s = std::sin(2.0 * pi * q / S);
+        if (q == 0) { c = 1.0; s = 0.0; }
+        if (4 * q == S) { c = 0.0; s = 1.0; }
+        if (2 * q == S) { c = -1.0; s = 0.0; }
+        tr[q] = c;
+        ti[q] = -s;
+        if (q > 0 && 2 * q < S) {
+            tr[S - q] = c;
+            ti[S - q] = s;
+        }
+    }
+    std::vector<float> t((size_t)2 * S * S);
+    for (int m = 0; m < S; ++m)
+        for (int k = 0; k < S; ++k) {
+            const int q = (m * k) % S;
+            t[2 * ((size_t)m * S + k)] = (float)tr[q];
+            t[2 * ((size_t)m * S + k) + 1] = (float)ti[q];
         }
     return t;
 }
@@ -208,59 +237,53 @@ struct fsr_context {
     int device = 0;
     std::mutex mu;
     std::mutex batch_mu;
-    float* freq_w = nullptr;
-    uint16_t* mfma_tab = nullptr;          // split-bf16 DFT operands
-    std::map<uint32_t, float*> rho_pow;   // keyed by the bits of rho
+    std::map<int, float*> freq_w;          // keyed by S
+    std::map<int, float*> dft_sg;          // DFT tables of the smaller supports, by S
+    uint16_t* mfma_tab = nullptr;          // split-bf16 DFT operands (S = 32)
+    std::map<uint64_t, float*> rho_pow;    // keyed by S << 32 | bits of rho
     fsr::BatchState batch;
 };
 
 namespace fsr {
 
-fsr_status context_tables(fsr_context* ctx, float rho, BlockTables* out) {
+// Uploads a host table once; `slot` caches the device copy.
+template <typename T>
+static fsr_status upload_table(const std::vector<T>& h, T** slot, const char* what) {
+    if (*slot) return FSR_OK;
+    T* d = nullptr;
+    hipError_t e = hipMalloc(&d, h.size() * sizeof(T));
+    if (e != hipSuccess) return fail(FSR_ERR_OUT_OF_MEMORY, "hipMalloc(%s): %s", what, hipGetErrorString(e));
+    e = hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return hip_fail(e, what);
+    }
+    *slot = d;
+    return FSR_OK;
+}
+
+fsr_status context_tables(fsr_context* ctx, int S, float rho, BlockTables* out) {
     std::lock_guard<std::mutex> lock(ctx->mu);
-    if (!ctx->freq_w) {
-        std::vector<float> h = host_freq_w();
-        float* d = nullptr;
-        hipError_t e = hipMalloc(&d, h.size() * sizeof(float));
-        if (e != hipSuccess) return fail(FSR_ERR_OUT_OF_MEMORY, "hipMalloc(freq table): %s", hipGetErrorString(e));
-        e = hipMemcpy(d, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice);
-        if (e != hipSuccess) {
-            (void)hipFree(d);
-            return hip_fail(e, "upload of frequency table");
+    fsr_status st;
+    *out = BlockTables{};
+    if ((st = upload_table(host_freq_w(S), &ctx->freq_w[S], "frequency table")) != FSR_OK) return st;
+    if (S == kS) {
+        if (!ctx->mfma_tab) {
+            std::vector<uint16_t> t;
+            dft_table(t);
+            if ((st = upload_table(t, &ctx->mfma_tab, "dft table")) != FSR_OK) return st;
         }
-        ctx->freq_w = d;
+    } else if ((st = upload_table(host_dft_sg(S), &ctx->dft_sg[S], "dft table")) != FSR_OK) {
+        return st;
     }
-    if (!ctx->mfma_tab) {
-        std::vector<uint16_t> t;
-        dft_table(t);
-        uint16_t* d = nullptr;
-        hipError_t e = hipMalloc(&d, t.size() * sizeof(uint16_t));
-        if (e != hipSuccess) return fail(FSR_ERR_OUT_OF_MEMORY, "hipMalloc(dft table): %s", hipGetErrorString(e));
-        e = hipMemcpy(d, t.data(), t.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
-        if (e != hipSuccess) {
-            (void)hipFree(d);
-            return hip_fail(e, "upload of dft table");
-        }
-        ctx->mfma_tab = d;
-    }
-    uint32_t key;
-    std::memcpy(&key, &rho, sizeof key);
-    auto it = ctx->rho_pow.find(key);
-    if (it == ctx->rho_pow.end()) {
-        std::vector<float> h = host_rho_pow(rho);
-        float* d = nullptr;
-        hipError_t e = hipMalloc(&d, h.size() * sizeof(float));
-        if (e != hipSuccess) return fail(FSR_ERR_OUT_OF_MEMORY, "hipMalloc(weight table): %s", hipGetErrorString(e));
-        e = hipMemcpy(d, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice);
-        if (e != hipSuccess) {
-            (void)hipFree(d);
-            return hip_fail(e, "upload of weight table");
-        }
-        it = ctx->rho_pow.emplace(key, d).first;
-    }
-    out->rho_pow = it->second;
-    out->freq_w = ctx->freq_w;
-    out->mfma_dft = ctx->mfma_tab;
+    uint32_t bits;
+    std::memcpy(&bits, &rho, sizeof bits);
+    const uint64_t key = ((uint64_t)(uint32_t)S << 32) | bits;
+    if ((st = upload_table(host_rho_pow(S, rho), &ctx->rho_pow[key], "weight table")) != FSR_OK) return st;
+    out->rho_pow = ctx->rho_pow[key];
+    out->freq_w = ctx->freq_w[S];
+    out->mfma_dft = S == kS ? ctx->mfma_tab : nullptr;
+    out->dft_sg = S == kS ? nullptr : reinterpret_cast<const float2*>(ctx->dft_sg[S]);
     return FSR_OK;
 }
 
@@ -330,9 +353,13 @@ fsr_status fsr_context_destroy(fsr_context* ctx) {
     {
         DeviceGuard g(ctx->device);
         release_batch_state(ctx->batch);
-        if (ctx->freq_w) (void)hipFree(ctx->freq_w);
+        for (auto& kv : ctx->freq_w)
+            if (kv.second) (void)hipFree(kv.second);
+        for (auto& kv : ctx->dft_sg)
+            if (kv.second) (void)hipFree(kv.second);
         if (ctx->mfma_tab) (void)hipFree(ctx->mfma_tab);
-        for (auto& kv : ctx->rho_pow) (void)hipFree(kv.second);
+        for (auto& kv : ctx->rho_pow)
+            if (kv.second) (void)hipFree(kv.second);
     }
     delete ctx;
     return FSR_OK;
@@ -350,11 +377,14 @@ fsr_status fsr_reconstruct(fsr_context* ctx, const float* image, const uint8_t* 
 
     if ((params->flags & FSR_FLAG_LDS_ARGMAX) && params->dft != FSR_DFT_FP32)
         return fail(FSR_ERR_UNSUPPORTED, "the LDS argmax runs with FSR_DFT_FP32 only");
+    const int S = params->block + 2 * params->border;
+    if (S != kS && (params->dft != FSR_DFT_FP32 || params->flags != 0))
+        return fail(FSR_ERR_UNSUPPORTED, "support %d runs with FSR_DFT_FP32 and no flags only", S);
 
     DeviceGuard g(ctx->device);
     if (g.error() != hipSuccess) return hip_fail(g.error(), "hipSetDevice");
     PlainLaunch p{};
-    if ((st = context_tables(ctx, params->rho, &p.tab)) != FSR_OK) return st;
+    if ((st = context_tables(ctx, S, params->rho, &p.tab)) != FSR_OK) return st;
     p.img.image = image;
     p.img.mask = mask;
     p.img.out = out;
@@ -367,6 +397,7 @@ fsr_status fsr_reconstruct(fsr_context* ctx, const float* image, const uint8_t* 
     p.img.block_begin = 0;
     p.block = params->block;
     p.border = params->border;
+    p.support = S;
     p.gamma = params->gamma;
     p.n_blocks = fsr_num_blocks(height, width, params->block);
     p.dft = params->dft == FSR_DFT_SPLIT_BF16 ? 1 : 0;

@@ -122,6 +122,8 @@ fsr_status prepare(fsr_context* ctx, const fsr_image_desc* descs, int32_t n, con
     if ((st = check_supported(params)) != FSR_OK) return st;
     if (params->flags & FSR_FLAG_LDS_ARGMAX)
         return errorf(FSR_ERR_UNSUPPORTED, "the LDS argmax runs in fsr_reconstruct only");
+    if (params->block + 2 * params->border != kS)
+        return errorf(FSR_ERR_UNSUPPORTED, "the batched path runs support size 32 only");
     if ((st = check_schedule(schedule)) != FSR_OK) return st;
     if ((st = plan_batch(descs, n, params, plan)) != FSR_OK) return st;
     if (!workspace && n > 0) return errorf(FSR_ERR_INVALID_ARG, "workspace is NULL");
@@ -220,7 +222,7 @@ fsr_status batched_enqueue(fsr_context* ctx, const fsr_image_desc* descs, int32_
     if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
     if (cap != hipStreamCaptureStatusNone)
         return errorf(FSR_ERR_UNSUPPORTED, "stream is being captured: use fsr_batch_graph_create");
-    if ((st = context_tables(ctx, params->rho, &prep.launch.tab)) != FSR_OK) return st;
+    if ((st = context_tables(ctx, kS, params->rho, &prep.launch.tab)) != FSR_OK) return st;
     if (slot_mutex) {
         std::lock_guard<std::mutex> lock(*slot_mutex);
         if ((st = upload_async(plan, workspace, stream, slot)) != FSR_OK) return st;
@@ -277,7 +279,7 @@ fsr_status fsr_batch_autotune(fsr_context* ctx, const fsr_image_desc* descs, int
     DeviceGuard g(context_device(ctx));
     if (g.error() != hipSuccess) return hip_fail(g.error(), "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
-    if ((st = context_tables(ctx, params->rho, &prep.launch.tab)) != FSR_OK) return st;
+    if ((st = context_tables(ctx, kS, params->rho, &prep.launch.tab)) != FSR_OK) return st;
     {
         std::lock_guard<std::mutex> lock(context_batch_mutex(ctx));
         if ((st = upload_async(plan, workspace, s, &context_batch(ctx).staging)) != FSR_OK) return st;
@@ -326,7 +328,7 @@ fsr_status fsr_batch_graph_create(fsr_context* ctx, const fsr_image_desc* descs,
     if (st != FSR_OK) return st;
     DeviceGuard g(context_device(ctx));
     if (g.error() != hipSuccess) return hip_fail(g.error(), "hipSetDevice");
-    if ((st = context_tables(ctx, params->rho, &prep.launch.tab)) != FSR_OK) return st;
+    if ((st = context_tables(ctx, kS, params->rho, &prep.launch.tab)) != FSR_OK) return st;
     hipError_t e;
     if (!plan.table.empty()) {
         e = hipMemcpy(static_cast<char*>(workspace) + kCtrlBytes, plan.table.data(),

@@ -1,0 +1,262 @@
+// fsr_block_sg.h -- one support block of FSR on one wavefront for the smaller
+// even supports S = 8, 16, 24 (Sec. II; the paper sweeps S over 8..32 in
+// Sec. IV and runs its real-time table at S = 16).
+//
+// Layout: G = 64 / S lane groups; lane = c + S h (c < S, h < G) is active
+// when lane < G S (all 64 lanes for S = 8 and 16, 48 for S = 24).  Slot s of
+// an active lane holds pixel (m = G s + h, n = c) of the tile, and bin
+// (k = G s + h, l = c) of a spectrum, so the bin index k S + l = s G S + lane
+// orders as (slot, lane), as in the S = 32 kernel.
+//
+// DFT: direct separable sums against a DFT table F[m][k] = exp(-j 2 pi m k / S)
+// held in LDS, built on the host with exact symmetries (F[m][S-k] is the
+// exact conjugate of F[m][k]).  Bins k and -k are then summed by the same
+// instruction sequence on exactly conjugated operands, so the FP32 spectrum
+// of a real tile is bitwise Hermitian without a symmetrisation step (the
+// rounding of a negated operand is the negated rounding).
+//
+// LDS per wavefront, 6 S^2 floats: the DFT table (S^2 float2), then a
+// scratch area that holds the tile and the first pass of the DFT, and
+// afterwards W with duplicated rows (2S x S float2).
+#pragma once
+
+#include "fsr_block.h"
+
+namespace fsr {
+
+template <int S>
+struct SgShape {
+    static constexpr int G = 64 / S;          // lane groups
+    static constexpr int NS = S / G;          // slots per lane
+    static constexpr int NL = G * S;          // active lanes
+    static constexpr int kLdsFloats = 6 * S * S;
+    static constexpr uint32_t kModMagic = (65536u + S - 1) / S;
+    static_assert(S % 2 == 0 && S >= 8 && S < 32 && S % G == 0, "even S in [8, 32)");
+    static_assert(NS <= 16, "slot code fits in 4 bits");
+};
+
+// q mod S for 0 <= q < 2 S^2 (the target-model phase index): a mask for
+// powers of two, else a multiply-shift division checked at compile time.
+template <int S>
+constexpr bool mod_magic_exact() {
+    for (uint32_t q = 0; q < 2u * S * S; ++q)
+        if (q - S * ((q * SgShape<S>::kModMagic) >> 16) != q % S) return false;
+    return true;
+}
+
+template <int S>
+__device__ __forceinline__ int mod_small(int q) {
+    if constexpr ((S & (S - 1)) == 0) {
+        return q & (S - 1);
+    } else {
+        static_assert(mod_magic_exact<S>(), "division by multiply-shift must be exact");
+        return q - S * (int)(((uint32_t)q * SgShape<S>::kModMagic) >> 16);
+    }
+}
+
+// 2D DFT of the real values v (slot s = pixel (G s + h, c)) into (re, im)
+// (slot s = bin (G s + h, c)).  Active lanes only carry data; inactive lanes
+// compute duplicates that the caller discards.  `ftab` is the DFT table in
+// LDS, `scr` the scratch area (tile: S^2 floats, then the first pass as
+// S^2 float2).
+template <int S>
+__device__ __forceinline__ void dft2_sg(const float (&v)[SgShape<S>::NS], float (&re)[SgShape<S>::NS],
+                                        float (&im)[SgShape<S>::NS], const float2* ftab, float* scr,
+                                        int c, int h, bool active) {
+    constexpr int G = SgShape<S>::G, NS = SgShape<S>::NS;
+    float* tile = scr;                                      // [m][n]
+    float2* pass1 = reinterpret_cast<float2*>(scr + S * S);  // [k][n]
+    if (active) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) tile[(G * s + h) * S + c] = v[s];
+    }
+    wave_sync();
+    // pass 1 along m: C[k][n] = sum_m x[m][n] F[m][k], k = G s + h, n = c
+    float ar[NS], ai[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) ar[s] = ai[s] = 0.0f;
+    // the row loops are only partly unrolled: fully unrolled, the compiler
+    // hoists all S x NS table reads ahead of the arithmetic
+#pragma unroll 2
+    for (int m = 0; m < S; ++m) {
+        const float x = tile[m * S + c];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const float2 f = ftab[m * S + G * s + h];
+            ar[s] = fmaf(x, f.x, ar[s]);
+            ai[s] = fmaf(x, f.y, ai[s]);
+        }
+    }
+    if (active) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) pass1[(G * s + h) * S + c] = make_float2(ar[s], ai[s]);
+    }
+    wave_sync();
+    // pass 2 along n: X[k][l] = sum_n C[k][n] F[n][l], k = G s + h, l = c
+    float br[NS], bi[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) br[s] = bi[s] = 0.0f;
+#pragma unroll 2
+    for (int n = 0; n < S; ++n) {
+        const float2 f = ftab[n * S + c];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const float2 a = pass1[(G * s + h) * S + n];
+            br[s] = fmaf(a.x, f.x, br[s]);
+            br[s] = fmaf(-a.y, f.y, br[s]);
+            bi[s] = fmaf(a.x, f.y, bi[s]);
+            bi[s] = fmaf(a.y, f.x, bi[s]);
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        re[s] = br[s];
+        im[s] = bi[s];
+    }
+    wave_sync();   // the scratch area is reused by the caller
+}
+
+template <int S>
+__device__ __forceinline__ void reconstruct_block_sg(const BlockJob& jb, int B, int L, float gamma,
+                                                     const BlockTables& tab, float* lds) {
+    constexpr int G = SgShape<S>::G, NS = SgShape<S>::NS, NL = SgShape<S>::NL;
+    const int lane = (int)(threadIdx.x & 63);
+    const bool active = lane < NL;
+    // inactive lanes (S = 24) get an in-range (c, h) so that every LDS
+    // address they form stays inside the tables
+    const int c = active ? lane % S : lane - NL;
+    const int h = active ? lane / S : 0;
+    const int y0 = jb.by * B - L, x0 = jb.bx * B - L;
+    float2* ftab = reinterpret_cast<float2*>(lds);
+    float* scr = lds + 2 * S * S;
+
+    // ---- DFT table into LDS (S^2 float2, the same for every block)
+    for (int i = lane; i < S * S; i += 64) ftab[i] = tab.dft_sg[i];
+
+    // ---- gather and weighting: slot s holds pixel (G s + h, c)
+    float xr[NS], wr[NS];
+    uint64_t any_known = 0;
+    const int x = x0 + c;
+    const bool xin = active && (unsigned)x < (unsigned)jb.width;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int m = G * s + h, y = y0 + m;
+        const bool in = xin && (unsigned)y < (unsigned)jb.height;
+        const int64_t off = in ? (int64_t)y * jb.stride + x : 0;
+        const uint8_t kraw = jb.mask[off];
+        const float fraw = jb.image[off];
+        const float rp = tab.rho_pow[m * S + c];
+        const uint8_t k = in ? kraw : (uint8_t)0;
+        any_known |= ballot(k != 0);
+        xr[s] = k ? fraw : 0.0f;
+        wr[s] = k ? rp : 0.0f;
+    }
+
+    // ---- target pixel owned by this lane (lanes 0 .. B*B-1)
+    const int ti = lane / B, tj = lane - (lane / B) * B;
+    const int tm = L + ti, tn = L + tj;
+    float acc = 0.0f;
+    const int iters = jb.iterations;
+    wave_sync();   // DFT table written
+
+    if (any_known != 0) {
+        // R_w = mu W + DFT2((f~ - mu) w), as in the S = 32 kernel
+        float sx = 0.0f, sw = 0.0f;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            sx = fmaf(xr[s], wr[s], sx);
+            sw += wr[s];
+        }
+        sx = wave_sum_f32(sx);
+        sw = wave_sum_f32(sw);
+        const float mu = sw > 0.0f ? sx / sw : 0.0f;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) xr[s] = (xr[s] - mu) * wr[s];
+        float xi[NS], wi[NS];
+        dft2_sg<S>(xr, xr, xi, ftab, scr, c, h, active);
+        dft2_sg<S>(wr, wr, wi, ftab, scr, c, h, active);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            xr[s] = fmaf(mu, wr[s], xr[s]);
+            xi[s] = fmaf(mu, wi[s], xi[s]);
+        }
+        // W with duplicated rows: row r holds W[r mod S]
+        float2* wtab = reinterpret_cast<float2*>(scr);
+        if (active) {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const int k = G * s + h;
+                wtab[k * S + c] = make_float2(wr[s], wi[s]);
+                wtab[(k + S) * S + c] = make_float2(wr[s], wi[s]);
+            }
+        }
+        const float w00 = readlane_f(wr[0], 0);
+        const float gi = w00 > 0.0f ? gamma / w00 : 0.0f;
+        float wf[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) wf[s] = tab.freq_w[(G * s + h) * S + c];
+        // lane i (< S) of tw_re / tw_im holds F[1][i] = exp(-j 2 pi i / S)
+        const float2 tw = ftab[S + (lane % S)];
+        const int tw_re = __float_as_int(tw.x), tw_im = __float_as_int(tw.y);
+        wave_sync();
+
+        for (int it = 0; it < iters; ++it) {
+            // objective key (Eq. 16), as in the S = 32 kernel: float32 bits
+            // with the 4 low mantissa bits replaced by 15 - slot
+            uint32_t lmax = 0;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const float e = fmaf(xr[s], xr[s], xi[s] * xi[s]);
+                const uint32_t key = (__float_as_uint(e * wf[s]) & 0xFFFFFFF0u) | (uint32_t)(15 - s);
+                lmax = umax(lmax, key);
+            }
+            if (!active) lmax = 0;   // real keys carry a slot code >= 4
+            const uint32_t mx = wave_max_u32(lmax);
+            const int ln = (int)__builtin_ctzll(ballot(lmax == mx));
+            const int slot = 15 - (int)(mx & 15u);
+            const int u = G * slot + ln / S, v = ln % S;
+            const int idx = u * S + v;
+            const float pr = readlane_f(xr[slot], ln);
+            const float pim = readlane_f(xi[slot], ln);
+            const float cr = gi * pr, ci = gi * pim;    // gamma * p (Eqs. 10-11)
+            if (jb.log != nullptr && lane == 0) jb.log[it] = (uint16_t)idx;
+
+            // model: g += gamma p exp(+j 2 pi (u m + v n) / S) on the target
+            const int q = mod_small<S>(u * tm + v * tn);
+            const float er = __int_as_float(__builtin_amdgcn_ds_bpermute(4 * q, tw_re));
+            const float ei = __int_as_float(__builtin_amdgcn_ds_bpermute(4 * q, tw_im));
+            acc = fmaf(cr, er, acc);
+            acc = fmaf(ci, ei, acc);
+
+            // residual (Eqs. 12, 14-15): slot s reads duplicated row
+            // (h - u) mod S + G s, column (c - v) mod S
+            int r0 = h - u, col = c - v;
+            r0 += r0 < 0 ? S : 0;
+            col += col < 0 ? S : 0;
+            const float2* wrow = wtab + (r0 * S + col);
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const float2 w = wrow[G * S * s];
+                xr[s] = fmaf(-cr, w.x, xr[s]);
+                xr[s] = fmaf(ci, w.y, xr[s]);
+                xi[s] = fmaf(-cr, w.y, xi[s]);
+                xi[s] = fmaf(-ci, w.x, xi[s]);
+            }
+        }
+        wave_sync();
+    } else if (jb.log != nullptr) {
+        for (int it = lane; it < iters; it += 64) jb.log[it] = (uint16_t)0xFFFF;
+    }
+
+    // ---- compose (Sec. II): known pixels copied, unknown pixels Re g
+    if (lane < B * B) {
+        const int y = jb.by * B + ti, xx = jb.bx * B + tj;
+        if (y < jb.height && xx < jb.width) {
+            const int64_t off = (int64_t)y * jb.stride + xx;
+            const uint8_t k = jb.mask[off];
+            jb.out[off] = k ? jb.image[off] : acc;
+        }
+    }
+}
+
+}  // namespace fsr

@@ -9,12 +9,15 @@ namespace fsr {
 constexpr int kS = 32;            // support edge handled by these kernels
 constexpr int kBins = kS * kS;    // 1024 frequency bins per block
 
-// Device tables for one (S = 32, rho) pair: the spatial weight rho^dist
-// (Eq. 5 before masking) and the frequency weight w_f (Eq. 9), both S x S,
-// row-major, float32.
+// Device tables for one (S, rho) pair: the spatial weight rho^dist (Eq. 5
+// before masking) and the frequency weight w_f (Eq. 9), both S x S,
+// row-major, float32, and the DFT operands of the support size.
 struct BlockTables {
-    const float* rho_pow;   // [m * 32 + n]
-    const float* freq_w;    // [k * 32 + l]
+    const float* rho_pow;   // [m * S + n]
+    const float* freq_w;    // [k * S + l]
+    // S < 32: F[m][k] = exp(-j 2 pi m k / S), S x S float2, exactly
+    // conjugate-symmetric in k
+    const float2* dft_sg;
     // DFT-matrix operands of the split-bf16 matrix-core transform in MFMA
     // lane order, bf16 bit patterns [part 2][q 2][term kMfmaMaxTerms][lane 64][8]
     const uint16_t* mfma_dft;
@@ -38,7 +41,8 @@ struct ImageDesc {
 
 struct PlainLaunch {
     ImageDesc img;
-    int32_t block, border;  // B, L with B + 2L = 32
+    int32_t block, border;  // B, L
+    int32_t support;        // S = B + 2L: 32, or 8, 16, 24 (fsr_block_sg.h)
     float gamma;
     BlockTables tab;
     int64_t n_blocks;

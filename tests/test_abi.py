@@ -68,9 +68,13 @@ def test_reconstruct_validates_before_touching_the_device(lib):
     assert _call(lib, fake_ctx, img, msk, ctypes.c_void_p(0x10000 + 64), 8, 8, 8, p) == binding.FSR_ERR_INVALID_ARG
     # out overlapping mask
     assert _call(lib, fake_ctx, img, msk, ctypes.c_void_p(0x20000000 + 8), 8, 8, 8, p) == binding.FSR_ERR_INVALID_ARG
-    # valid but outside this build: support 16
-    p16 = fsr.make_params(block=4, border=6)
-    assert _call(lib, fake_ctx, img, msk, out, 8, 8, 8, p16) == binding.FSR_ERR_UNSUPPORTED
+    # valid but outside this build: support 12 and 20
+    for p_other in (fsr.make_params(block=4, border=4), fsr.make_params(block=4, border=8)):
+        assert _call(lib, fake_ctx, img, msk, out, 8, 8, 8, p_other) == binding.FSR_ERR_UNSUPPORTED
+    # the smaller supports run with the FP32 DFT and no flags only
+    for kw in (dict(dft=fsr.FSR_DFT_SPLIT_BF16), dict(flags=fsr.FSR_FLAG_LDS_ARGMAX)):
+        p16 = fsr.make_params(block=4, border=6, **kw)
+        assert _call(lib, fake_ctx, img, msk, out, 8, 8, 8, p16) == binding.FSR_ERR_UNSUPPORTED
     assert _call(lib, fake_ctx, img, msk, out, 8, 8, 8, fsr.make_params(block=12, border=10)) == binding.FSR_ERR_UNSUPPORTED
     # the LDS-argmax ablation runs with the FP32 FFTs only
     lds_bf16 = fsr.make_params(flags=fsr.FSR_FLAG_LDS_ARGMAX, dft=fsr.FSR_DFT_SPLIT_BF16)

@@ -1,0 +1,116 @@
+"""Supports S = 8, 16 and 24 (fsr_block_sg.h) against the FP64 oracle.
+
+Same acceptance bars as the S = 32 path: known pixels bitwise, |gpu - oracle|
+<= 1 code value on >= 99.9 % of the unknown pixels, PSNR gap <= 0.05 dB,
+argmax agreement >= 99 % of the logged (block, iteration) pairs, the oracle
+deciding at kernel precision.  The frames span many blocks and every
+B x L split listed, including L = 0 and ragged edges.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth.metrics import parity_report
+
+torch = pytest.importorskip("torch")
+import paper_2202_13926_amd as fsr  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+KERNEL = oracle.DECISION_KERNEL
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return fsr.Context(0)
+
+
+def run(ctx, img, mask, params):
+    ti = torch.from_numpy(np.ascontiguousarray(img, np.float32)).to(DEV)
+    tm = torch.from_numpy(np.ascontiguousarray(mask, np.uint8)).to(DEV)
+    out, lg = fsr.reconstruct(ti, tm, params, ctx=ctx, log=True)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), lg.cpu().numpy().view(np.uint16)[:, :params.iterations]
+
+
+def check(rep, name):
+    print(f"[parity] {name}: {rep}", flush=True)
+    assert rep["known_bitwise"]
+    assert rep["frac_le_1"] >= 0.999
+    assert rep["psnr_gap"] <= 0.05
+    if "argmax_agree" in rep:
+        assert rep["argmax_agree"] >= 0.99
+
+
+def exhaustive(ctx, img, mask, B, L, iters, name, rho=0.7, gamma=0.5):
+    img32 = img.astype(np.float32)
+    p = fsr.make_params(block=B, border=L, iterations=iters, rho=rho, gamma=gamma)
+    g, gl = run(ctx, img32, mask, p)
+    o, ol, n_empty = oracle.reconstruct(img32.astype(np.float64), mask, iters, block_size=B,
+                                        border=L, rho=rho, gamma=gamma, log=True, decision=KERNEL)
+    check(parity_report(img32, mask, g, o, gl if iters else None, ol if iters else None), name)
+    return g, gl, ol, n_empty
+
+
+@pytest.mark.parametrize("B,L", [(4, 2), (8, 0), (2, 3), (4, 6), (8, 4), (6, 5), (4, 10), (8, 8), (6, 9)])
+def test_supports_exhaustive(ctx, B, L):
+    S = B + 2 * L
+    print(f"\n[gpu case] S = {S} (B = {B}, L = {L}), 96x100 quarter frame, I = 100, every pixel",
+          flush=True)
+    img, mask = synth.make_image(96, 100, 300 + S + B), synth.quarter_mask(96, 100, 301 + S + B)
+    exhaustive(ctx, img, mask, B, L, 100, f"S{S} B{B}")
+
+
+@pytest.mark.parametrize("S", [8, 16, 24])
+def test_concealment_mask_and_more_iterations(ctx, S):
+    print(f"\n[gpu case] S = {S}, 128x128 concealment mask, I = 200", flush=True)
+    img, mask = synth.make_image(128, 128, 400 + S), synth.macroblock_mask(128, 128, 401 + S)
+    exhaustive(ctx, img, mask, 4, (S - 4) // 2, 200, f"S{S} concealment")
+
+
+def test_s16_full_hd_sampled(ctx):
+    print("\n[gpu case] S = 16 on the 1920x1080 quarter frame, oracle on 3000 sampled blocks",
+          flush=True)
+    w = synth.workload("fhd_quarter")
+    img, mask = w.inputs()
+    img32 = img.astype(np.float32)
+    p = fsr.make_params(block=4, border=6, iterations=100)
+    g, gl = run(ctx, img32, mask, p)
+    assert np.array_equal(g[mask != 0], img32[mask != 0]) and np.all(np.isfinite(g))
+    n = fsr.fsr_num_blocks(1080, 1920, 4)
+    ids = np.array(sorted(np.random.default_rng(21).choice(n, size=3000, replace=False).tolist()))
+    ot, ol, _, _ = oracle.reconstruct_blocks(img32.astype(np.float64), mask, ids, 100, block_size=4,
+                                             border=6, log=True, decision=KERNEL)
+
+    def targets(frame):
+        t = np.full((len(ids), 4, 4), np.nan)
+        for i, b in enumerate(ids):
+            by, bx = divmod(int(b), 480)
+            t[i] = frame[by * 4:by * 4 + 4, bx * 4:bx * 4 + 4]
+        return t
+    check(parity_report(targets(img32), targets(mask.astype(np.float64)), targets(g), ot, gl[ids], ol),
+          "S16 fhd sampled")
+
+
+@pytest.mark.parametrize("S", [8, 16, 24])
+def test_small_support_edge_cases(ctx, S):
+    print(f"\n[gpu case] S = {S}: empty supports, I = 0, ragged 37x50, fully known, repeat", flush=True)
+    B, L = 4, (S - 4) // 2
+    img, mask = synth.make_image(96, 96, 9), synth.quarter_mask(96, 96, 10)
+    mask[8:88, 8:88] = 0
+    g, gl, ol, n_empty = exhaustive(ctx, img, mask, B, L, 25, f"S{S} hole")
+    assert n_empty > 0
+    empty = np.all(ol == 0xFFFF, axis=1)
+    assert np.all(gl[empty] == 0xFFFF)
+    g0, _ = run(ctx, img, mask, fsr.make_params(block=B, border=L, iterations=0))
+    assert np.all(g0[mask == 0] == 0.0)
+    img2, mask2 = synth.make_image(37, 50, 41), synth.quarter_mask(37, 50, 42)
+    exhaustive(ctx, img2, mask2, B, L, 60, f"S{S} ragged")
+    img32 = img2.astype(np.float32)
+    g1, _ = run(ctx, img32, np.ones_like(mask2), fsr.make_params(block=B, border=L, iterations=10))
+    assert np.array_equal(g1, img32)
+    a = run(ctx, img2, mask2, fsr.make_params(block=B, border=L, iterations=60))
+    b = run(ctx, img2, mask2, fsr.make_params(block=B, border=L, iterations=60))
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
