@@ -84,6 +84,9 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=2400,
                     help="requests of the served comparison (0 skips it); the stated workload "
                          "is 10,000 (about 42 s per mode)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="only run the paper's 640-point parameter grid (S, I, rho, gamma) on a "
+                         "1200x1200 frame and print it as one JSON object")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (a kernel of known "
                          "traffic, used to scale the FETCH_SIZE / WRITE_SIZE counters)")
@@ -236,6 +239,50 @@ def bench_multiresolution(ctx, steps: int = 5):
     for S in (8, 16, 24, 32):
         res["fhd_ms_by_support"][f"S={S}"] = round(frame_ms(1080, 1920, 4, (S - 4) // 2, 1800), 4)
     return res
+
+
+def parameter_sweep(ctx, size: int = 1200, steps: int = 3):
+    """The paper's parameter grid (Sec. IV): I in {100, ..., 400}, S in
+    {8, 16, 24, 32} (B = 4), rho in {0.68, ..., 0.82}, gamma in {0.2, ..., 0.6}:
+    640 parameterisations on one size x size synthetic frame with a
+    quarter-sampling mask.  Returns time per frame and PSNR (missing pixels
+    and full frame, against the ground-truth frame) for each."""
+    import torch
+
+    import paper_2202_13926_amd as fsr
+    import synth
+    from synth.metrics import psnr
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    img = synth.make_image(size, size, 2100).astype(np.float32)
+    mask = synth.quarter_mask(size, size, 2101)
+    ti = torch.from_numpy(img).to(dev)
+    tm = torch.from_numpy(mask).to(dev)
+    o = torch.empty_like(ti)
+    rows = []
+    for S in (8, 16, 24, 32):
+        for iters in (100, 200, 300, 400):
+            for rho in np.round(np.arange(0.68, 0.8201, 0.02), 2):
+                for gamma in np.round(np.arange(0.2, 0.6001, 0.1), 1):
+                    p = fsr.make_params(block=4, border=(S - 4) // 2, iterations=iters,
+                                        rho=float(rho), gamma=float(gamma))
+                    fsr.fsr_reconstruct(ctx, ti, tm, o, p, None, stream)
+                    torch.cuda.synchronize()
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    for _ in range(steps):
+                        fsr.fsr_reconstruct(ctx, ti, tm, o, p, None, stream)
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    g = o.cpu().numpy()
+                    rows.append({"S": S, "I": iters, "rho": float(rho), "gamma": float(gamma),
+                                 "ms": round(e0.elapsed_time(e1) / steps, 4),
+                                 "psnr_missing_db": round(psnr(img, g, mask == 0), 3),
+                                 "psnr_db": round(psnr(img, g), 3)})
+    return {"workload": f"{size}x{size} synthetic frame, quarter-sampling mask, B=4",
+            "parameterisations": len(rows), "rows": rows}
 
 
 def bench_batched(ctx, steps: int = 5):
@@ -400,6 +447,12 @@ def main():
 
     import paper_2202_13926_amd as fsr
     import synth
+
+    if args.sweep:
+        ctx = fsr.Context(0)
+        print(json.dumps(parameter_sweep(ctx)), flush=True)
+        ctx.close()
+        return
 
     w = synth.workload(WORKLOAD)
     img, mask = w.inputs()

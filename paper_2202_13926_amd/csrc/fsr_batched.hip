@@ -44,7 +44,7 @@ __device__ __forceinline__ void batch_block(const BatchLaunch& p, int64_t g, int
     jb.by = (int32_t)(local / d.nbx);
     jb.bx = (int32_t)(local % d.nbx);
     jb.iterations = d.iterations;
-    reconstruct_block<kDft, kArgmaxWave>(jb, p.block, p.border, p.gamma, p.tab, lds);
+    reconstruct_block<kDft, kArgmaxWave, true>(jb, p.block, p.border, p.gamma, p.tab, lds);
 }
 
 template <int kWaves, int kDft>

@@ -19,8 +19,8 @@
 // rows duplicated (64 rows x 32 bins x float2) so that the rows a lane needs
 // for its 16 bins, (k - u) mod 32 for k = 2s + h, form one contiguous run and
 // every slot's address is the lane's base plus an immediate offset.  The
-// same buffer first serves as the transpose scratch of the DFTs (lower half)
-// and as the parking place of the first spectrum (upper half).
+// same buffer first serves as the transpose scratch of the DFTs and, in the
+// persistent kernel, as the parking place of the first spectrum (upper half).
 #pragma once
 
 #include "fsr_device.h"
@@ -32,16 +32,18 @@ namespace fsr {
 // Reads the 2D spectrum left in the transpose planes into the bin layout,
 // (k, l) = (2s + h, c), with exact Hermitian symmetrisation
 // X[k, l] <- (X[k, l] + conj X[-k, -l]) / 2.
+template <bool kSwizzle>
 __device__ __forceinline__ void planes_to_bins(float (&xr)[16], float (&xi)[16], float* lds, int lane) {
+    using P = Planes<kSwizzle>;
     const int c = lane & 31, h = lane >> 5;
-    const float* pr = plane_re(lds);
-    const float* pi = plane_im(lds);
+    const float* pr = P::re(lds);
+    const float* pi = P::im(lds);
     const int lm = (kS - c) & 31;
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
         const int k = 2 * s + h, km = (kS - k) & 31;
-        const float ar = pr[pidx(k, c)], ai = pi[pidx(k, c)];
-        const float br = pr[pidx(km, lm)], bi = pi[pidx(km, lm)];
+        const float ar = pr[P::idx(k, c)], ai = pi[P::idx(k, c)];
+        const float br = pr[P::idx(km, lm)], bi = pi[P::idx(km, lm)];
         xr[s] = 0.5f * (ar + br);
         xi[s] = 0.5f * (ai - bi);
     }
@@ -50,39 +52,40 @@ __device__ __forceinline__ void planes_to_bins(float (&xr)[16], float (&xi)[16],
 
 // 2D DFT of the real tile v (spatial layout) into the bin layout, exactly
 // Hermitian.  Leaves (re, im) of bins 64*s + lane in (xr, xi).  Uses the
-// lower 8 KiB of the block's LDS only.
+// transpose planes at the start of the block's LDS only.
+template <bool kSwizzle>
 __device__ __forceinline__ void dft2_real_to_bins(float (&xr)[16], float (&xi)[16], float* lds,
                                                   int lane) {
+    using P = Planes<kSwizzle>;
     const int c = lane & 31, h = lane >> 5;
-    float* pr = plane_re(lds);
-    float* pi = plane_im(lds);
+    float* pr = P::re(lds);
+    float* pi = P::im(lds);
 #pragma unroll
     for (int s = 0; s < 16; ++s) xi[s] = 0.0f;
     // pass 1: along m (rows of the tile) for every column n = c
     dft32_lane_pair(xr, xi, h);                 // slot k' -> bin row k = k' + 16h, column n = c
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-        pr[pidx(k + 16 * h, c)] = xr[k];
-        pi[pidx(k + 16 * h, c)] = xi[k];
+        pr[P::idx(k + 16 * h, c)] = xr[k];
+        pi[P::idx(k + 16 * h, c)] = xi[k];
     }
     wave_sync();
     // pass 2: along n for every k = c; slot s takes n = 2s + h
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
-        xr[s] = pr[pidx(c, 2 * s + h)];
-        xi[s] = pi[pidx(c, 2 * s + h)];
+        xr[s] = pr[P::idx(c, 2 * s + h)];
+        xi[s] = pi[P::idx(c, 2 * s + h)];
     }
     wave_sync();
     dft32_lane_pair(xr, xi, h);                 // slot l' -> (k = c, l = l' + 16h)
 #pragma unroll
     for (int l = 0; l < 16; ++l) {
-        pr[pidx(c, l + 16 * h)] = xr[l];
-        pi[pidx(c, l + 16 * h)] = xi[l];
+        pr[P::idx(c, l + 16 * h)] = xr[l];
+        pi[P::idx(c, l + 16 * h)] = xi[l];
     }
     wave_sync();
-    planes_to_bins(xr, xi, lds, lane);
+    planes_to_bins<kSwizzle>(xr, xi, lds, lane);
 }
-
 
 // Everything a block needs to know about its image and the method.
 struct BlockJob {
@@ -115,18 +118,24 @@ __device__ __forceinline__ uint2 better_pair(uint2 a, uint2 b) {
     return (b.x > a.x || (b.x == a.x && b.y < a.y)) ? b : a;
 }
 
-template <int kDft, int kArgmax = kArgmaxWave>
+// kPersistent: the caller loops over blocks (the persistent batched
+// kernel).  Its per-block values are then made opaque, so that the compiler
+// does not hoist the table loads and lane constants out of the caller's loop
+// and keep them live across every block, and the first spectrum is parked
+// in the upper half of the LDS (swizzled transpose planes) while the second
+// is transformed.  A one-block wavefront keeps both spectra in registers and
+// uses the padded planes, whose addresses are immediates.
+template <int kDft, int kArgmax, bool kPersistent>
 __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int L, float gamma,
                                                   const BlockTables& tab_in, float* lds,
                                                   uint2* argmax_lds = nullptr) {
-    // Per-block values are made opaque so that a caller looping over blocks
-    // (the persistent kernel) does not hoist the table loads and lane
-    // constants out of its loop and keep them live across every block.
-    const int lane = opaque((int)(threadIdx.x & 63));
-    BlockTables tab;
-    tab.rho_pow = opaque_ptr(tab_in.rho_pow);
-    tab.freq_w = opaque_ptr(tab_in.freq_w);
-    tab.mfma_dft = kDft == kDftSplitBf16 ? opaque_ptr(tab_in.mfma_dft) : nullptr;
+    const int lane = kPersistent ? opaque((int)(threadIdx.x & 63)) : (int)(threadIdx.x & 63);
+    BlockTables tab = tab_in;
+    if constexpr (kPersistent) {
+        tab.rho_pow = opaque_ptr(tab_in.rho_pow);
+        tab.freq_w = opaque_ptr(tab_in.freq_w);
+        if constexpr (kDft == kDftSplitBf16) tab.mfma_dft = opaque_ptr(tab_in.mfma_dft);
+    }
     const int c = lane & 31, h = lane >> 5;
     const int y0 = jb.by * B - L, x0 = jb.bx * B - L;
 
@@ -181,23 +190,27 @@ __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int
         auto dft2 = [&](float (&re)[16], float (&im)[16]) {
             if constexpr (kDft == kDftSplitBf16)
                 dft2_real_mfma(re, im, reinterpret_cast<const bf16x8*>(tab.mfma_dft), lane);
-            else dft2_real_to_bins(re, im, lds, lane);
+            else dft2_real_to_bins<kPersistent>(re, im, lds, lane);
         };
         dft2(xr, xi);
-        // park the first spectrum in the upper half of the LDS while the
-        // second is transformed, so both never occupy registers at once
-        float2* pk = park(lds);
+        if constexpr (kPersistent) {
+            // park the first spectrum in the upper half of the LDS while the
+            // second is transformed, so both never occupy registers at once
+            float2* pk = park(lds);
 #pragma unroll
-        for (int s = 0; s < 16; ++s) pk[64 * s + lane] = make_float2(xr[s], xi[s]);
-        wave_sync();
-        dft2(wr, wi);
+            for (int s = 0; s < 16; ++s) pk[64 * s + lane] = make_float2(xr[s], xi[s]);
+            wave_sync();
+            dft2(wr, wi);
 #pragma unroll
-        for (int s = 0; s < 16; ++s) {
-            const float2 v = pk[64 * s + lane];
-            xr[s] = v.x;
-            xi[s] = v.y;
+            for (int s = 0; s < 16; ++s) {
+                const float2 v = pk[64 * s + lane];
+                xr[s] = v.x;
+                xi[s] = v.y;
+            }
+            wave_sync();
+        } else {
+            dft2(wr, wi);
         }
-        wave_sync();
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
             xr[s] = fmaf(mu, wr[s], xr[s]);

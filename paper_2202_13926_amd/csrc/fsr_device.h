@@ -22,14 +22,26 @@ constexpr int kSlots = 16;        // bins (or pixels) per lane
 // ---------------------------------------------------------------- LDS of a block
 constexpr int kLdsFloats = 2 * 64 * kS;   // 4096 floats = 16 KiB
 
-// Transpose scratch: two planes (re, im) of 32 x 32 floats in the lower
-// 8 KiB.  Element (r, j) lives at r * 32 + (j ^ r): rows and columns both
-// map to 32 distinct banks, so row-wise and column-wise accesses of a
-// half-wavefront are conflict-free.  The upper 8 KiB can hold one spectrum
-// in bin layout (see park()).
-__device__ __forceinline__ float* plane_re(float* lds) { return lds; }
-__device__ __forceinline__ float* plane_im(float* lds) { return lds + kS * kS; }
-__device__ __forceinline__ int pidx(int r, int j) { return r * kS + (j ^ r); }
+// Transpose scratch of the FFTs: two planes (re, im) of 32 x 32 floats.
+// Two layouts:
+//  * padded (kSwizzle = false): element (r, j) at 33 r + j.  Rows and
+//    columns of a half-wavefront hit 32 distinct banks and every address is
+//    a lane base plus an immediate; the planes take 8.25 KiB.
+//  * swizzled (kSwizzle = true): element (r, j) at 32 r + (j xor r), also
+//    conflict-free by rows and columns, in exactly 8 KiB, so that the upper
+//    8 KiB can hold one spectrum in bin layout (see park()) -- at the price
+//    of an xor per address.
+template <bool kSwizzle>
+struct Planes {
+    static constexpr int kPitch = kSwizzle ? kS : kS + 1;
+    static __device__ __forceinline__ float* re(float* lds) { return lds; }
+    static __device__ __forceinline__ float* im(float* lds) { return lds + kS * kPitch; }
+    static __device__ __forceinline__ int idx(int r, int j) {
+        return kSwizzle ? r * kS + (j ^ r) : r * kPitch + j;
+    }
+};
+static_assert(2 * kS * Planes<false>::kPitch <= kLdsFloats, "padded planes fit the block's LDS");
+
 __device__ __forceinline__ float2* park(float* lds) {
     return reinterpret_cast<float2*>(lds + 2 * kS * kS);
 }

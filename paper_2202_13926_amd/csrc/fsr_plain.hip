@@ -32,7 +32,7 @@ template <int kDft, int kArgmax>
 __global__ __launch_bounds__(64) void fsr_plain_s32(PlainLaunch p) {
     __shared__ __align__(16) float lds[kLdsFloats + (kArgmax == kArgmaxLds ? kArgmaxLdsFloats : 0)];
     const int64_t blk = xcd_contiguous(blockIdx.x, p.n_blocks);
-    reconstruct_block<kDft, kArgmax>(plain_job(p, blk), p.block, p.border, p.gamma, p.tab, lds,
+    reconstruct_block<kDft, kArgmax, false>(plain_job(p, blk), p.block, p.border, p.gamma, p.tab, lds,
                                      reinterpret_cast<uint2*>(lds + kLdsFloats));
 }
 
