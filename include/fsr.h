@@ -82,7 +82,9 @@ enum {
  *   block >= 1, border >= 0, S = block + 2*border even and <= 32,
  *   iterations >= 0, 0 < rho <= 1, 0 < gamma <= 1 (Sec. II), flags a
  *   combination of FSR_FLAG_*.
- * This build runs S = 32 with block <= 8 (FSR_ERR_UNSUPPORTED otherwise).
+ * This build runs S in {8, 16, 24, 32} with block <= 8 (FSR_ERR_UNSUPPORTED
+ * otherwise); the batched and served paths, FSR_DFT_SPLIT_BF16 and
+ * FSR_FLAG_LDS_ARGMAX run S = 32 only.
  */
 typedef struct fsr_params {
     int32_t block;       /* B: target block edge in pixels                  */
