@@ -1,10 +1,11 @@
 // fsr_batched.hip -- many images of different sizes and iteration counts in
 // one launch.  Blocks of all images form one index space in queue order
 // (heaviest images first); wavefronts either take one block each (chunk 0,
-// a plain grid) or run persistently, popping `chunk` consecutive blocks at a
-// time from a global counter until the index space is exhausted.  Each block
-// runs exactly the same routine as the one-image kernel, so its result does
-// not depend on the batch it is part of.
+// a plain grid: fsr_batched_grid_s32) or run persistently, popping `chunk`
+// consecutive blocks at a time from a global counter until the index space
+// is exhausted (fsr_batched_s32).  Each block runs the same arithmetic as in
+// the one-image kernel, so its result does not depend on the batch it is
+// part of.
 #include "fsr_block.h"
 
 namespace fsr {
@@ -29,7 +30,7 @@ __device__ __forceinline__ void locate(const BatchLaunch& p, int64_t g, int& img
     end = lo + 1 < p.n_images ? p.descs[lo + 1].block_begin : p.total_blocks;
 }
 
-template <int kDft>
+template <int kDft, bool kPersistent>
 __device__ __forceinline__ void batch_block(const BatchLaunch& p, int64_t g, int img, float* lds) {
     const DevDesc& d = p.descs[img];
     const int64_t local = g - d.block_begin;
@@ -44,30 +45,40 @@ __device__ __forceinline__ void batch_block(const BatchLaunch& p, int64_t g, int
     jb.by = (int32_t)(local / d.nbx);
     jb.bx = (int32_t)(local % d.nbx);
     jb.iterations = d.iterations;
-    reconstruct_block<kDft, kArgmaxWave, true>(jb, p.block, p.border, p.gamma, p.tab, lds);
+    reconstruct_block<kDft, kArgmaxWave, kPersistent>(jb, p.block, p.border, p.gamma, p.tab, lds);
 }
 
+// Plain grid (chunk 0): one block per wavefront, no loop, so the block
+// routine runs in its one-block form (padded planes, both spectra in
+// registers), as in the one-image kernel.
+template <int kWaves, int kDft>
+__global__ __launch_bounds__(64 * kWaves) void fsr_batched_grid_s32(BatchLaunch p) {
+    __shared__ __align__(16) float lds[kWaves * kLdsFloats];
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t groups = (p.total_blocks + kWaves - 1) / kWaves;
+    const int64_t g = xcd_contiguous(blockIdx.x, groups) * kWaves + wave;
+    if (g >= p.total_blocks) return;
+    int img = 0;
+    int64_t img_begin = 0, img_end = 0;
+    locate(p, g, img, img_begin, img_end);
+    batch_block<kDft, false>(p, g, img, lds + wave * kLdsFloats);
+}
+
+// Persistent (chunk > 0): wavefronts pop `chunk` blocks at a time.
 template <int kWaves, int kDft>
 __global__ __launch_bounds__(64 * kWaves) void fsr_batched_s32(BatchLaunch p) {
-    __shared__ float lds[kWaves * kLdsFloats];
+    __shared__ __align__(16) float lds[kWaves * kLdsFloats];
     // wave-uniform by construction; readfirstlane lets the compiler see it,
     // so block indices and descriptors stay in scalar registers
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     float* mine = lds + wave * kLdsFloats;
-    // [next, end): blocks this wavefront still owns.  Without a queue a
-    // wavefront owns exactly one block; with one it refills from the queue.
+    // [next, end): blocks this wavefront still owns; refilled from the queue
     int64_t next = 0, end = 0;
     int img = 0;
     int64_t img_begin = 0, img_end = 0;   // empty: the first block searches
-    if (p.chunk <= 0) {
-        const int64_t groups = (p.total_blocks + kWaves - 1) / kWaves;
-        next = xcd_contiguous(blockIdx.x, groups) * kWaves + wave;
-        end = next < p.total_blocks ? next + 1 : next;
-    }
     for (;;) {
         if (next >= end) {
-            if (p.chunk <= 0) break;
             unsigned start = 0;
             if (lane == 0) start = atomicAdd(p.counter, (unsigned)p.chunk);
             start = __builtin_amdgcn_readfirstlane(start);
@@ -77,7 +88,7 @@ __global__ __launch_bounds__(64 * kWaves) void fsr_batched_s32(BatchLaunch p) {
             if (end > p.total_blocks) end = p.total_blocks;
         }
         locate(p, next, img, img_begin, img_end);
-        batch_block<kDft>(p, next, img, mine);
+        batch_block<kDft, true>(p, next, img, mine);
         ++next;
     }
 }
@@ -85,10 +96,20 @@ __global__ __launch_bounds__(64 * kWaves) void fsr_batched_s32(BatchLaunch p) {
 template <int kDft>
 static hipError_t launch_waves(const BatchLaunch& p, int waves_per_group, dim3 grid, dim3 block,
                                hipStream_t stream) {
+    const bool queue = p.chunk > 0;
     switch (waves_per_group) {
-    case 1: hipLaunchKernelGGL((fsr_batched_s32<1, kDft>), grid, block, 0, stream, p); break;
-    case 2: hipLaunchKernelGGL((fsr_batched_s32<2, kDft>), grid, block, 0, stream, p); break;
-    case 4: hipLaunchKernelGGL((fsr_batched_s32<4, kDft>), grid, block, 0, stream, p); break;
+    case 1:
+        if (queue) hipLaunchKernelGGL((fsr_batched_s32<1, kDft>), grid, block, 0, stream, p);
+        else hipLaunchKernelGGL((fsr_batched_grid_s32<1, kDft>), grid, block, 0, stream, p);
+        break;
+    case 2:
+        if (queue) hipLaunchKernelGGL((fsr_batched_s32<2, kDft>), grid, block, 0, stream, p);
+        else hipLaunchKernelGGL((fsr_batched_grid_s32<2, kDft>), grid, block, 0, stream, p);
+        break;
+    case 4:
+        if (queue) hipLaunchKernelGGL((fsr_batched_s32<4, kDft>), grid, block, 0, stream, p);
+        else hipLaunchKernelGGL((fsr_batched_grid_s32<4, kDft>), grid, block, 0, stream, p);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
