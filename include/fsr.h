@@ -56,10 +56,12 @@ typedef enum fsr_status {
 } fsr_status;
 
 /* How the two forward block DFTs of Eq. 7 are computed; the iterations are
- * FP32 either way.  FSR_DFT_SPLIT_BF16 runs them as 32 x 32 DFT-matrix
- * products on the matrix cores (bf16 inputs, FP32 accumulation) with every
- * operand split into three bf16 terms (hi + mid + lo, 6 products per real
- * product), which keeps the spectra as accurate as the FP32 FFT's. */
+ * FP32 either way.  FSR_DFT_SPLIT_BF16 (the precision variant) runs them as
+ * 32 x 32 DFT-matrix products on the matrix cores (bf16 inputs, FP32
+ * accumulation) with every operand split into three bf16 terms (hi + mid +
+ * lo, 6 products per real product), which keeps the spectra as accurate as
+ * the FP32 FFT's, and sums the model terms of the target pixels with
+ * compensation (Kahan). */
 enum {
     FSR_DFT_FP32 = 0,        /* FP32 in-register FFT on the vector ALUs    */
     FSR_DFT_SPLIT_BF16 = 1   /* split-bf16 DFT-matrix products on MFMA     */

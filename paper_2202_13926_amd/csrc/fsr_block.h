@@ -10,7 +10,8 @@
 //   loop       I times: objective w_f |R_w|^2 (Eq. 16), wave argmax with
 //              ties to the smaller bin, p = R_w[u,v] / W[0,0] (Eq. 10), model
 //              update accumulated directly into the target pixels (Eq. 11
-//              followed by the inverse DFT restricted to the target), residual
+//              followed by the inverse DFT restricted to the target; a
+//              compensated sum in the split-bf16 variant), residual
 //              update R_w -= gamma p W[k-u, l-v] with cyclic indices
 //              (Eqs. 12, 14-15)
 //   compose    known target pixels copied, unknown ones take Re g
@@ -166,6 +167,8 @@ __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int
     const int ti = lane / B, tj = lane - (lane / B) * B;
     const int tm = L + ti, tn = L + tj;
     float acc = 0.0f;
+    // running compensation of acc (Kahan), kept by the precision variant
+    float acc_comp = 0.0f;
     const int iters = jb.iterations;
 
     if (any_known != 0) {
@@ -193,7 +196,11 @@ __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int
             else dft2_real_to_bins<kPersistent>(re, im, lds, lane);
         };
         dft2(xr, xi);
-        if constexpr (kPersistent) {
+        // the matrix-core transform parks too: with both spectra live across
+        // it, the register allocator splits the spectrum arrays and the
+        // loop's indexed read of the winning bin then copies them each
+        // iteration
+        if constexpr (kPersistent || kDft == kDftSplitBf16) {
             // park the first spectrum in the upper half of the LDS while the
             // second is transformed, so both never occupy registers at once
             float2* pk = park(lds);
@@ -292,8 +299,16 @@ __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int
             const int q4 = mad_u24(v, tn4, mul_u24(u, tm4)) & 124;
             const float er = __int_as_float(__builtin_amdgcn_ds_bpermute(q4, tw_re));
             const float ei = __int_as_float(__builtin_amdgcn_ds_bpermute(q4, tw_im));
-            acc = fmaf(cr, er, acc);
-            acc = fmaf(ci, ei, acc);
+            if constexpr (kDft == kDftSplitBf16) {
+                // compensated sum of the I model terms
+                const float y = fmaf(cr, er, ci * ei) - acc_comp;
+                const float t = acc + y;
+                acc_comp = (t - acc) - y;
+                acc = t;
+            } else {
+                acc = fmaf(cr, er, acc);
+                acc = fmaf(ci, ei, acc);
+            }
 
             // residual: R_w[k,l] -= gamma p W[(k-u) mod S, (l-v) mod S]; slot s
             // reads duplicated row (h - u) mod 32 + 2s at byte offset 512 s
@@ -320,7 +335,7 @@ __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int
         if (y < jb.height && xx < jb.width) {
             const int64_t off = (int64_t)y * jb.stride + xx;
             const uint8_t k = jb.mask[off];
-            jb.out[off] = k ? jb.image[off] : acc;
+            jb.out[off] = k ? jb.image[off] : acc - acc_comp;
         }
     }
 }
