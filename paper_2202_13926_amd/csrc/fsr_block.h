@@ -3,10 +3,11 @@
 // Steps (Regensky et al., Sec. II and III-A):
 //   gather     support tile at (by*B - L, bx*B - L); pixels outside the image
 //              or masked out are unknown: f~ = 0, w = 0            (Eqs. 2, 5)
-//   DFT        R_w = DFT2(f~ w), W = DFT2(w): in-register FFTs along the
-//              slot axis with LDS transposes between the passes, or two
-//              split-bf16 matrix products on the matrix cores; then exact
-//              Hermitian symmetrisation X <- (X + conj X[-k]) / 2   (Eq. 7)
+//   DFT        R_w = DFT2(f~ w), W = DFT2(w) (Eq. 7): one complex FFT of
+//              both real tiles (in-register FFTs along the slot axis, an LDS
+//              transpose between the passes) split into two exactly
+//              Hermitian spectra; or split-bf16 matrix products on the
+//              matrix cores, then X <- (X + conj X[-k]) / 2
 //   loop       I times: objective w_f |R_w|^2 (Eq. 16), wave argmax with
 //              ties to the smaller bin, p = R_w[u,v] / W[0,0] (Eq. 10), model
 //              update accumulated directly into the target pixels (Eq. 11
@@ -30,12 +31,48 @@
 
 namespace fsr {
 
-// Reads the 2D spectrum left in the transpose planes into the bin layout,
-// (k, l) = (2s + h, c), with exact Hermitian symmetrisation
-// X[k, l] <- (X[k, l] + conj X[-k, -l]) / 2.
-template <bool kSwizzle>
-__device__ __forceinline__ void planes_to_bins(float (&xr)[16], float (&xi)[16], float* lds, int lane) {
-    using P = Planes<kSwizzle>;
+// 2D DFT of the complex tile z = (zr, zi) (spatial layout) into the
+// transpose planes: Z[k][l] at Planes::idx(k, l).  In-register FFTs along
+// the slot axis, an LDS transpose between the passes.
+__device__ __forceinline__ void dft2_complex_to_planes(float (&zr)[16], float (&zi)[16], float* lds,
+                                                       int lane) {
+    using P = Planes;
+    const int c = lane & 31, h = lane >> 5;
+    float* pr = P::re(lds);
+    float* pi = P::im(lds);
+    // pass 1: along m (rows of the tile) for every column n = c
+    dft32_lane_pair(zr, zi, h);                 // slot k' -> bin row k = k' + 16h, column n = c
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        pr[P::idx(k + 16 * h, c)] = zr[k];
+        pi[P::idx(k + 16 * h, c)] = zi[k];
+    }
+    wave_sync();
+    // pass 2: along n for every k = c; slot s takes n = 2s + h
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        zr[s] = pr[P::idx(c, 2 * s + h)];
+        zi[s] = pi[P::idx(c, 2 * s + h)];
+    }
+    wave_sync();
+    dft32_lane_pair(zr, zi, h);                 // slot l' -> (k = c, l = l' + 16h)
+#pragma unroll
+    for (int l = 0; l < 16; ++l) {
+        pr[P::idx(c, l + 16 * h)] = zr[l];
+        pi[P::idx(c, l + 16 * h)] = zi[l];
+    }
+    wave_sync();
+}
+
+// Splits Z = F2{x + j s w} of two real tiles, left in the planes, into the
+// bin layouts of X = F2{x} = (Z + conj Z[-k]) / 2 and
+// W = F2{w} = (Z - conj Z[-k]) / (2 j s), with half_inv_s = 1 / (2 s) exact
+// (s a power of two).  Bins k and -k read the same pair of values in swapped
+// roles, so both spectra come out exactly Hermitian.
+__device__ __forceinline__ void planes_split_two_real(float (&xr)[16], float (&xi)[16], float (&wr)[16],
+                                                      float (&wi)[16], float half_inv_s, float* lds,
+                                                      int lane) {
+    using P = Planes;
     const int c = lane & 31, h = lane >> 5;
     const float* pr = P::re(lds);
     const float* pi = P::im(lds);
@@ -47,45 +84,10 @@ __device__ __forceinline__ void planes_to_bins(float (&xr)[16], float (&xi)[16],
         const float br = pr[P::idx(km, lm)], bi = pi[P::idx(km, lm)];
         xr[s] = 0.5f * (ar + br);
         xi[s] = 0.5f * (ai - bi);
+        wr[s] = (ai + bi) * half_inv_s;
+        wi[s] = (br - ar) * half_inv_s;
     }
     wave_sync();
-}
-
-// 2D DFT of the real tile v (spatial layout) into the bin layout, exactly
-// Hermitian.  Leaves (re, im) of bins 64*s + lane in (xr, xi).  Uses the
-// transpose planes at the start of the block's LDS only.
-template <bool kSwizzle>
-__device__ __forceinline__ void dft2_real_to_bins(float (&xr)[16], float (&xi)[16], float* lds,
-                                                  int lane) {
-    using P = Planes<kSwizzle>;
-    const int c = lane & 31, h = lane >> 5;
-    float* pr = P::re(lds);
-    float* pi = P::im(lds);
-#pragma unroll
-    for (int s = 0; s < 16; ++s) xi[s] = 0.0f;
-    // pass 1: along m (rows of the tile) for every column n = c
-    dft32_lane_pair(xr, xi, h);                 // slot k' -> bin row k = k' + 16h, column n = c
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        pr[P::idx(k + 16 * h, c)] = xr[k];
-        pi[P::idx(k + 16 * h, c)] = xi[k];
-    }
-    wave_sync();
-    // pass 2: along n for every k = c; slot s takes n = 2s + h
-#pragma unroll
-    for (int s = 0; s < 16; ++s) {
-        xr[s] = pr[P::idx(c, 2 * s + h)];
-        xi[s] = pi[P::idx(c, 2 * s + h)];
-    }
-    wave_sync();
-    dft32_lane_pair(xr, xi, h);                 // slot l' -> (k = c, l = l' + 16h)
-#pragma unroll
-    for (int l = 0; l < 16; ++l) {
-        pr[P::idx(c, l + 16 * h)] = xr[l];
-        pi[P::idx(c, l + 16 * h)] = xi[l];
-    }
-    wave_sync();
-    planes_to_bins<kSwizzle>(xr, xi, lds, lane);
 }
 
 // Everything a block needs to know about its image and the method.
@@ -190,24 +192,19 @@ __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int
 #pragma unroll
         for (int s = 0; s < 16; ++s) xr[s] = (xr[s] - mu) * wr[s];
         float xi[16], wi[16];
-        auto dft2 = [&](float (&re)[16], float (&im)[16]) {
-            if constexpr (kDft == kDftSplitBf16)
-                dft2_real_mfma(re, im, reinterpret_cast<const bf16x8*>(tab.mfma_dft), lane);
-            else dft2_real_to_bins<kPersistent>(re, im, lds, lane);
-        };
-        dft2(xr, xi);
-        // the matrix-core transform parks too: with both spectra live across
-        // it, the register allocator splits the spectrum arrays and the
-        // loop's indexed read of the winning bin then copies them each
-        // iteration
-        if constexpr (kPersistent || kDft == kDftSplitBf16) {
+        if constexpr (kDft == kDftSplitBf16) {
+            const bf16x8* fop = reinterpret_cast<const bf16x8*>(tab.mfma_dft);
+            dft2_real_mfma(xr, xi, fop, lane);
             // park the first spectrum in the upper half of the LDS while the
-            // second is transformed, so both never occupy registers at once
+            // second is transformed: with both spectra live across the
+            // transform, the register allocator splits the spectrum arrays
+            // and the loop's indexed read of the winning bin then copies them
+            // every iteration
             float2* pk = park(lds);
 #pragma unroll
             for (int s = 0; s < 16; ++s) pk[64 * s + lane] = make_float2(xr[s], xi[s]);
             wave_sync();
-            dft2(wr, wi);
+            dft2_real_mfma(wr, wi, fop, lane);
 #pragma unroll
             for (int s = 0; s < 16; ++s) {
                 const float2 v = pk[64 * s + lane];
@@ -216,7 +213,24 @@ __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int
             }
             wave_sync();
         } else {
-            dft2(wr, wi);
+            // both real tiles in one complex FFT: z = x + j s w, with s the
+            // power of two at or below max |x|, so that the scaling is exact
+            // and neither part is small beside the other (the FFT's
+            // rounding is shared between them in proportion to their sizes)
+            uint32_t amax = 0;
+#pragma unroll
+            for (int s = 0; s < 16; s += 2) {
+                const float m2 = fmaxf(fabsf(xr[s]), fabsf(xr[s + 1]));
+                amax = umax(amax, __float_as_uint(m2));
+            }
+            amax = wave_max_u32(amax);
+            const uint32_t sbits = amax & 0x7F800000u;
+            const float scale = sbits ? __uint_as_float(sbits) : 1.0f;
+            const float half_inv_s = 0.5f / scale;
+#pragma unroll
+            for (int s = 0; s < 16; ++s) xi[s] = wr[s] * scale;
+            dft2_complex_to_planes(xr, xi, lds, lane);
+            planes_split_two_real(xr, xi, wr, wi, half_inv_s, lds, lane);
         }
 #pragma unroll
         for (int s = 0; s < 16; ++s) {

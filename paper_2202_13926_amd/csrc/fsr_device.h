@@ -22,26 +22,19 @@ constexpr int kSlots = 16;        // bins (or pixels) per lane
 // ---------------------------------------------------------------- LDS of a block
 constexpr int kLdsFloats = 2 * 64 * kS;   // 4096 floats = 16 KiB
 
-// Transpose scratch of the FFTs: two planes (re, im) of 32 x 32 floats.
-// Two layouts:
-//  * padded (kSwizzle = false): element (r, j) at 33 r + j.  Rows and
-//    columns of a half-wavefront hit 32 distinct banks and every address is
-//    a lane base plus an immediate; the planes take 8.25 KiB.
-//  * swizzled (kSwizzle = true): element (r, j) at 32 r + (j xor r), also
-//    conflict-free by rows and columns, in exactly 8 KiB, so that the upper
-//    8 KiB can hold one spectrum in bin layout (see park()) -- at the price
-//    of an xor per address.
-template <bool kSwizzle>
+// Transpose scratch of the FFTs: two planes (re, im) of 32 x 32 floats,
+// element (r, j) at 33 r + j: rows and columns of a half-wavefront hit 32
+// distinct banks and every address is a lane base plus an immediate.
 struct Planes {
-    static constexpr int kPitch = kSwizzle ? kS : kS + 1;
+    static constexpr int kPitch = kS + 1;
     static __device__ __forceinline__ float* re(float* lds) { return lds; }
     static __device__ __forceinline__ float* im(float* lds) { return lds + kS * kPitch; }
-    static __device__ __forceinline__ int idx(int r, int j) {
-        return kSwizzle ? r * kS + (j ^ r) : r * kPitch + j;
-    }
+    static __device__ __forceinline__ int idx(int r, int j) { return r * kPitch + j; }
 };
-static_assert(2 * kS * Planes<false>::kPitch <= kLdsFloats, "padded planes fit the block's LDS");
+static_assert(2 * kS * Planes::kPitch <= kLdsFloats, "planes fit the block's LDS");
 
+// Upper 8 KiB of the block's LDS: one spectrum in bin layout, parked while
+// the matrix-core path transforms the second.
 __device__ __forceinline__ float2* park(float* lds) {
     return reinterpret_cast<float2*>(lds + 2 * kS * kS);
 }
