@@ -6,8 +6,9 @@
 //   DFT        R_w = DFT2(f~ w), W = DFT2(w) (Eq. 7): one complex FFT of
 //              both real tiles (in-register FFTs along the slot axis, an LDS
 //              transpose between the passes) split into two exactly
-//              Hermitian spectra; or split-bf16 matrix products on the
-//              matrix cores, then X <- (X + conj X[-k]) / 2
+//              Hermitian spectra; or two split-bf16 matrix-product transforms
+//              on the matrix cores, each made Hermitian,
+//              X <- (X + conj X[-k]) / 2
 //   loop       I times: objective w_f |R_w|^2 (Eq. 16), wave argmax with
 //              ties to the smaller bin, p = R_w[u,v] / W[0,0] (Eq. 10), model
 //              update accumulated directly into the target pixels (Eq. 11
@@ -21,8 +22,9 @@
 // rows duplicated (64 rows x 32 bins x float2) so that the rows a lane needs
 // for its 16 bins, (k - u) mod 32 for k = 2s + h, form one contiguous run and
 // every slot's address is the lane's base plus an immediate offset.  The
-// same buffer first serves as the transpose scratch of the DFTs and, in the
-// persistent kernel, as the parking place of the first spectrum (upper half).
+// same buffer first serves as the transpose scratch of the FFTs, or, in the
+// matrix-core variant, holds the first spectrum (upper half) while the
+// second is transformed.
 #pragma once
 
 #include "fsr_device.h"
@@ -90,6 +92,25 @@ __device__ __forceinline__ void planes_split_two_real(float (&xr)[16], float (&x
     wave_sync();
 }
 
+// The FFT path takes the two real tiles x = (f~ - mu) w and w through one
+// complex transform of z = x + j s w, with s the power of two at or below
+// max |x| over the block: the scaling is exact and neither part is small
+// beside the other (a transform's rounding is shared between the parts in
+// proportion to their sizes).  Returns max |x| (wave-uniform) and s (1 when
+// x = 0).
+__device__ __forceinline__ float max_abs_and_scale(const float (&x)[16], float& scale) {
+    uint32_t amax = 0;
+#pragma unroll
+    for (int s = 0; s < 16; s += 2) {
+        const float m2 = fmaxf(fabsf(x[s]), fabsf(x[s + 1]));
+        amax = umax(amax, __float_as_uint(m2));
+    }
+    amax = wave_max_u32(amax);
+    const uint32_t sbits = amax & 0x7F800000u;
+    scale = sbits ? __uint_as_float(sbits) : 1.0f;
+    return __uint_as_float(amax);
+}
+
 // Everything a block needs to know about its image and the method.
 struct BlockJob {
     const float* image;
@@ -124,10 +145,7 @@ __device__ __forceinline__ uint2 better_pair(uint2 a, uint2 b) {
 // kPersistent: the caller loops over blocks (the persistent batched
 // kernel).  Its per-block values are then made opaque, so that the compiler
 // does not hoist the table loads and lane constants out of the caller's loop
-// and keep them live across every block, and the first spectrum is parked
-// in the upper half of the LDS (swizzled transpose planes) while the second
-// is transformed.  A one-block wavefront keeps both spectra in registers and
-// uses the padded planes, whose addresses are immediates.
+// and keep them live across every block.
 template <int kDft, int kArgmax, bool kPersistent>
 __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int L, float gamma,
                                                   const BlockTables& tab_in, float* lds,
@@ -193,13 +211,13 @@ __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int
         for (int s = 0; s < 16; ++s) xr[s] = (xr[s] - mu) * wr[s];
         float xi[16], wi[16];
         if constexpr (kDft == kDftSplitBf16) {
+            // two real transforms; the first spectrum waits in LDS while the
+            // second is computed.  (The one-transform split used below for
+            // the FFTs does not suit the matrix cores: there Z[k] and
+            // conj Z[-k] of a purely imaginary input do not cancel exactly,
+            // measured up to 2^-21 of max w, which leaks W's rounding into X.)
             const bf16x8* fop = reinterpret_cast<const bf16x8*>(tab.mfma_dft);
             dft2_real_mfma(xr, xi, fop, lane);
-            // park the first spectrum in the upper half of the LDS while the
-            // second is transformed: with both spectra live across the
-            // transform, the register allocator splits the spectrum arrays
-            // and the loop's indexed read of the winning bin then copies them
-            // every iteration
             float2* pk = park(lds);
 #pragma unroll
             for (int s = 0; s < 16; ++s) pk[64 * s + lane] = make_float2(xr[s], xi[s]);
@@ -213,24 +231,20 @@ __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int
             }
             wave_sync();
         } else {
-            // both real tiles in one complex FFT: z = x + j s w, with s the
-            // power of two at or below max |x|, so that the scaling is exact
-            // and neither part is small beside the other (the FFT's
-            // rounding is shared between them in proportion to their sizes)
-            uint32_t amax = 0;
-#pragma unroll
-            for (int s = 0; s < 16; s += 2) {
-                const float m2 = fmaxf(fabsf(xr[s]), fabsf(xr[s + 1]));
-                amax = umax(amax, __float_as_uint(m2));
-            }
-            amax = wave_max_u32(amax);
-            const uint32_t sbits = amax & 0x7F800000u;
-            const float scale = sbits ? __uint_as_float(sbits) : 1.0f;
-            const float half_inv_s = 0.5f / scale;
+            // both real tiles in one complex FFT: z = x + j s w
+            float scale;
+            const float xmax = max_abs_and_scale(xr, scale);
 #pragma unroll
             for (int s = 0; s < 16; ++s) xi[s] = wr[s] * scale;
             dft2_complex_to_planes(xr, xi, lds, lane);
-            planes_split_two_real(xr, xi, wr, wi, half_inv_s, lds, lane);
+            planes_split_two_real(xr, xi, wr, wi, 0.5f / scale, lds, lane);
+            if (xmax == 0.0f) {
+                // a support whose known pixels all equal mu (a flat or
+                // clipped region): X is exactly 0, and no rounding of the w
+                // part may leak into it (with mu = 0 it would be all of R_w)
+#pragma unroll
+                for (int s = 0; s < 16; ++s) xr[s] = xi[s] = 0.0f;
+            }
         }
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
@@ -257,6 +271,17 @@ __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int
         const int h256 = opaque(256 * h), c8 = opaque(8 * c);
         wave_sync();
 
+        // the residual spectrum lives in two 16-wide vectors during the
+        // loop: one contiguous register tuple each, which the indexed read
+        // of the winning bin needs (as separate floats the allocator may
+        // scatter them and then copy them into a tuple every iteration)
+        f32x16 vr, vi;
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            vr[s] = xr[s];
+            vi[s] = xi[s];
+        }
+
         for (int it = 0; it < iters; ++it) {
             // objective (Eq. 16) as an argmax key: the IEEE bits of the
             // non-negative float32 objective (so unsigned order is float
@@ -268,7 +293,7 @@ __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int
                 uint32_t lmax = 0;
 #pragma unroll
                 for (int s = 0; s < 16; ++s) {
-                    const float e = fmaf(xr[s], xr[s], xi[s] * xi[s]);
+                    const float e = fmaf(vr[s], vr[s], vi[s] * vi[s]);
                     const uint32_t key = (__float_as_uint(e * wf[s]) & 0xFFFFFFF0u) | (uint32_t)(15 - s);
                     lmax = umax(lmax, key);
                 }
@@ -278,7 +303,7 @@ __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int
             } else {
 #pragma unroll
                 for (int s = 0; s < 16; ++s) {
-                    const float e = fmaf(xr[s], xr[s], xi[s] * xi[s]);
+                    const float e = fmaf(vr[s], vr[s], vi[s] * vi[s]);
                     const uint32_t key = (__float_as_uint(e * wf[s]) & 0xFFFFFFF0u) | (uint32_t)(15 - s);
                     argmax_lds[64 * s + lane] = make_uint2(key, (uint32_t)(64 * s + lane));
                 }
@@ -303,8 +328,8 @@ __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int
                 wave_sync();   // the next iteration overwrites the pairs
             }
             const int slot = idx >> 6, ln = idx & 63;
-            const float pr = readlane_f(xr[slot], ln);
-            const float pim = readlane_f(xi[slot], ln);
+            const float pr = readlane_f(vr[slot], ln);
+            const float pim = readlane_f(vi[slot], ln);
             const int u = idx >> 5, v = idx & 31;
             const float cr = gi * pr, ci = gi * pim;    // gamma * p (Eqs. 10-11)
             if (jb.log != nullptr && lane == 0) jb.log[it] = (uint16_t)idx;
@@ -332,10 +357,10 @@ __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int
 #pragma unroll
             for (int s = 0; s < 16; ++s) {
                 const float2 w = wrow[64 * s];
-                xr[s] = fmaf(-cr, w.x, xr[s]);
-                xr[s] = fmaf(ci, w.y, xr[s]);
-                xi[s] = fmaf(-cr, w.y, xi[s]);
-                xi[s] = fmaf(-ci, w.x, xi[s]);
+                vr[s] = fmaf(-cr, w.x, vr[s]);
+                vr[s] = fmaf(ci, w.y, vr[s]);
+                vi[s] = fmaf(-cr, w.y, vi[s]);
+                vi[s] = fmaf(-ci, w.x, vi[s]);
             }
         }
         wave_sync();   // the LDS is reused by the next block of a persistent wave
