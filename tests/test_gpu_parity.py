@@ -255,3 +255,38 @@ def test_side_stream_matches_default_stream(ctx):
     with torch.cuda.stream(s):
         b, lb = run_gpu(ctx, img, mask, fsr.make_params(), stream=s)
     assert np.array_equal(a, b) and np.array_equal(la, lb)
+
+
+@pytest.mark.parametrize("dft", [fsr.FSR_DFT_FP32, fsr.FSR_DFT_SPLIT_BF16])
+def test_flat_and_clipped_regions(ctx, dft):
+    """Supports whose known pixels are all equal have x = (f~ - mu) w = 0
+    and R_w = mu W exactly.  Clipped black (mu = 0): every objective is 0,
+    the tie rule picks bin 0 each time, and the GPU must follow that
+    exactly -- no rounding of the weight transform may leak into the
+    residual spectrum.  Saturated white (mu = 255): the residual shrinks by
+    (1 - gamma) per pick while staying a multiple of W, until after about
+    20 picks FP32 rounding, not the method, sets the remaining decisions
+    (FP64 keeps it exact far longer).  Those late picks carry coefficients
+    of 1e-6 of the first one, so the output still matches; the decision
+    bar is applied to the other blocks."""
+    announce(f"flat and clipped regions, dft {dft}")
+    H, W = 96, 120
+    img = synth.make_image(H, W, 77)
+    img[:, :40] = 0.0
+    img[:, 80:] = 255.0
+    mask = synth.quarter_mask(H, W, 78)
+    img32 = img.astype(np.float32)
+    g, gl = run_gpu(ctx, img32, mask, fsr.make_params(iterations=60, dft=dft))
+    o, ol, _ = oracle.reconstruct(img32.astype(np.float64), mask, 60, log=True, decision=KERNEL)
+    nbx = W // 4
+    bx = np.arange(len(gl)) % nbx
+    black = bx * 4 + 18 <= 40            # support entirely in the black band
+    white = bx * 4 - 14 >= 80            # support entirely in the white band
+    rep = parity_report(img32, mask, g, o, gl[~white], ol[~white])
+    assert_parity(rep, f"flat regions dft{dft}")
+    assert np.all(gl[black] == 0) and np.array_equal(gl[black], ol[black])
+    assert np.all(g[:, :22][mask[:, :22] == 0] == 0.0)
+    # white supports: the first picks (the DC bin while the residual is
+    # still a clean multiple of W) agree, and the output is exact
+    assert np.array_equal(gl[white][:, :10], ol[white][:, :10])
+    assert np.max(np.abs(g[:, 98:] - 255.0)) < 1e-3
