@@ -43,7 +43,7 @@ def mirror(idx, S):
 
 
 # ---------------------------------------------------------------- P1: DFT convention
-@pytest.mark.parametrize("S", [4, 6, 8, 16, 32])
+@pytest.mark.parametrize("S", [4, 6, 8, 16, 24, 32])
 def test_dft_matches_numpy_fft2(oracle_lib, S):
     """O4 uses numpy's convention: unnormalised, exp(-j 2 pi (km + ln)/S), k along rows."""
     rng = np.random.default_rng(S)
@@ -55,13 +55,23 @@ def test_dft_matches_numpy_fft2(oracle_lib, S):
 
 
 def test_twiddle_table_exact_symmetry(oracle_lib):
-    for S in (8, 16, 32):
+    # reference in extended precision (x87 long double, 64-bit mantissa): a
+    # double-precision exp(-2j pi q / S) carries its own angle rounding (up
+    # to 1.5e-15 at q near S for S = 24).  The table itself is cos / sin of
+    # the double-rounded angle 2 pi q / S (q <= S/2, mirrored above): the
+    # angle's rounding (<= half an ulp of 2 pi, 4.4e-16) plus the libm
+    # rounding bound each entry's error by about 2 ulp of 1 (4.4e-16).
+    pi_l = np.longdouble("3.14159265358979323846264338327950288")
+    for S in (8, 16, 24, 32):
         t = oracle_lib.twiddles(S)
         assert t[0] == 1.0
         assert t[S // 4] == -1j and t[S // 2] == -1.0 and t[3 * S // 4] == 1j
         for q in range(1, S):
             assert t[S - q] == np.conj(t[q])
-        assert np.max(np.abs(t - np.exp(-2j * np.pi * np.arange(S) / S))) < 1e-15
+        ang = 2 * pi_l * np.arange(S, dtype=np.longdouble) / np.longdouble(S)
+        err_re = np.abs(t.real.astype(np.longdouble) - np.cos(ang))
+        err_im = np.abs(t.imag.astype(np.longdouble) + np.sin(ang))
+        assert float(max(err_re.max(), err_im.max())) <= 4.5e-16
 
 
 # ---------------------------------------------------------------- weights
@@ -87,8 +97,9 @@ def test_weights_closed_form(oracle_lib):
 
 
 # ---------------------------------------------------------------- P9: bitwise Hermitian
-def test_spectra_bitwise_hermitian(oracle_lib):
-    ft, known = random_support(32, 11)
+@pytest.mark.parametrize("S", [8, 16, 24, 32])
+def test_spectra_bitwise_hermitian(oracle_lib, S):
+    ft, known = random_support(S, 11)
     w = np_weight(known, 0.7)
     for x in (ft * w, w, ft):
         Xr, Xi = oracle_lib.dft2_real_parts(x)
@@ -96,7 +107,8 @@ def test_spectra_bitwise_hermitian(oracle_lib):
         Xi_m = np.roll(Xi[::-1, ::-1], 1, axis=(0, 1))
         assert np.array_equal(Xr, Xr_m)
         assert np.array_equal(Xi, -Xi_m)
-        for k, l in ((0, 0), (0, 16), (16, 0), (16, 16)):
+        h = S // 2
+        for k, l in ((0, 0), (0, h), (h, 0), (h, h)):
             assert Xi[k, l] == 0.0
 
 
@@ -144,12 +156,12 @@ def test_orthogonal_case_recovers_fft(oracle_lib):
 
 
 # ---------------------------------------------------------------- P3: energy descent
-@pytest.mark.parametrize("gamma", [0.3, 0.5, 1.0])
-def test_energy_descent_closed_form(oracle_lib, gamma):
+@pytest.mark.parametrize("gamma,S", [(0.3, 32), (0.5, 32), (1.0, 32), (0.5, 16), (0.5, 24)])
+def test_energy_descent_closed_form(oracle_lib, gamma, S):
     """E(v+1) = E(v) - (2 gamma - gamma^2) |R(v)[u,v]|^2 / W[0,0], with E the
     weighted spatial residual energy (Eqs. 3-4) of the model built from the
     logged picks, evaluated independently with numpy."""
-    S, I, rho = 32, 60, 0.7
+    I, rho = 60, 0.7
     ft, known = random_support(S, 21)
     res = oracle_lib.block(ft, known, I, rho, gamma)
     w = np_weight(known, rho)
@@ -173,9 +185,10 @@ def test_energy_descent_closed_form(oracle_lib, gamma):
 
 
 # ---------------------------------------------------------------- P4: residual consistency
-def test_residual_matches_definition(oracle_lib):
+@pytest.mark.parametrize("S", [16, 24, 32])
+def test_residual_matches_definition(oracle_lib, S):
     """After I iterations R_w == DFT2((f~ - g) w) (Eqs. 4, 6, 7 and linearity)."""
-    S, I, rho, gamma = 32, 80, 0.7, 0.5
+    I, rho, gamma = 80, 0.7, 0.5
     ft, known = random_support(S, 31)
     res = oracle_lib.block(ft, known, I, rho, gamma)
     w = np_weight(known, rho)
