@@ -41,12 +41,16 @@ MUTANTS = {
 PIN_CALLS = [
     lambda o: pins.test_dft_matches_numpy_fft2(o, 8),
     lambda o: pins.test_dft_matches_numpy_fft2(o, 32),
+    lambda o: pins.test_dft_matches_numpy_fft2(o, 24),
     pins.test_twiddle_table_exact_symmetry,
     pins.test_weights_closed_form,
-    pins.test_spectra_bitwise_hermitian,
+    lambda o: pins.test_spectra_bitwise_hermitian(o, 32),
+    lambda o: pins.test_spectra_bitwise_hermitian(o, 24),
     pins.test_orthogonal_case_recovers_fft,
-    lambda o: pins.test_energy_descent_closed_form(o, 0.5),
-    pins.test_residual_matches_definition,
+    lambda o: pins.test_energy_descent_closed_form(o, 0.5, 32),
+    lambda o: pins.test_energy_descent_closed_form(o, 0.5, 24),
+    lambda o: pins.test_residual_matches_definition(o, 32),
+    lambda o: pins.test_residual_matches_definition(o, 24),
     lambda o: pins.test_first_step_matches_bruteforce_least_squares(o, 1),
     lambda o: pins.test_grid_sinusoid_recovered(o, 1, 2, 0.9),
     pins.test_fully_known_image_unchanged,
