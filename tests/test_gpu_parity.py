@@ -290,3 +290,41 @@ def test_flat_and_clipped_regions(ctx, dft):
     # still a clean multiple of W) agree, and the output is exact
     assert np.array_equal(gl[white][:, :10], ol[white][:, :10])
     assert np.max(np.abs(g[:, 98:] - 255.0)) < 1e-3
+
+
+@pytest.mark.parametrize("B,L", [(4, 14), (4, 6)])
+def test_pixel_offsets_beyond_32_bits(ctx, B, L):
+    """A 40 x 64 image stored with a row stride of 2^26 + 7 elements: the
+    last rows sit more than 2^31 elements (8 GiB of float32) past the first,
+    so every image, mask and output address needs 64-bit offsets.  About
+    24 GiB of device memory, almost all of it untouched padding."""
+    H, W, stride = 40, 64, (1 << 26) + 7
+    announce(f"row stride {stride}: offsets up to {(H - 1) * stride + W} elements, S = {B + 2 * L}")
+    img = synth.make_image(H, W, 61).astype(np.float32)
+    mask = synth.quarter_mask(H, W, 62)
+    dev = torch.device("cuda:0")
+    n = (H - 1) * stride + W
+    assert n > (1 << 31)
+    bi = torch.zeros(n, dtype=torch.float32, device=dev)
+    bm = torch.zeros(n, dtype=torch.uint8, device=dev)
+    bo = torch.full((n,), -3.0, dtype=torch.float32, device=dev)
+    ti = bi.as_strided((H, W), (stride, 1))
+    tm = bm.as_strided((H, W), (stride, 1))
+    to = bo.as_strided((H, W), (stride, 1))
+    ti.copy_(torch.from_numpy(img))
+    tm.copy_(torch.from_numpy(mask))
+    p = fsr.make_params(block=B, border=L, iterations=40)
+    nb = fsr.fsr_num_blocks(H, W, B)
+    lg = torch.empty((nb, 40), dtype=torch.int16, device=dev)
+    fsr.fsr_reconstruct(ctx, ti, tm, to, p, lg)
+    torch.cuda.synchronize()
+    g = to.cpu().numpy()
+    gl = lg.cpu().numpy().view(np.uint16)
+    assert float(bo[W]) == -3.0 and float(bo[n - W - 1]) == -3.0   # padding untouched
+    del bi, bm, bo, ti, tm, to
+    torch.cuda.empty_cache()
+    o, ol, _ = oracle.reconstruct(img.astype(np.float64), mask, 40, block_size=B, border=L,
+                                  log=True, decision=KERNEL)
+    rep = parity_report(img, mask, g, o, gl, ol)
+    assert_parity(rep, f"64-bit offsets S{B + 2 * L}")
+    assert np.array_equal(g[mask != 0], img[mask != 0])
