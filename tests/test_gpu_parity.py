@@ -328,3 +328,38 @@ def test_pixel_offsets_beyond_32_bits(ctx, B, L):
     rep = parity_report(img, mask, g, o, gl, ol)
     assert_parity(rep, f"64-bit offsets S{B + 2 * L}")
     assert np.array_equal(g[mask != 0], img[mask != 0])
+
+
+def test_concurrent_contexts_and_streams(ctx):
+    """Two host threads, each with its own context and stream, reconstruct
+    different frames at the same time (different parameters, one of them at
+    S = 16); each result equals the same call made alone."""
+    import threading
+    announce("two threads, two contexts, two streams")
+    cases = [(synth.make_image(200, 240, 81), synth.quarter_mask(200, 240, 82), fsr.make_params()),
+             (synth.make_image(160, 300, 83), synth.uniform_loss_mask(160, 300, 0.6, 84),
+              fsr.make_params(block=4, border=6, iterations=150, rho=0.8, gamma=0.4))]
+    alone = [run_gpu(ctx, img, mask, p) for img, mask, p in cases]
+    results = [None, None]
+    errors = []
+
+    def worker(k):
+        try:
+            c = fsr.Context(0)
+            s = torch.cuda.Stream()
+            img, mask, p = cases[k]
+            for _ in range(3):
+                with torch.cuda.stream(s):
+                    results[k] = run_gpu(c, img, mask, p, stream=s)
+            c.close()
+        except Exception as e:  # surfaced below
+            errors.append(e)
+
+    threads = [threading.Thread(target=worker, args=(k,)) for k in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    for (a, la), (b, lb) in zip(alone, results):
+        assert np.array_equal(a, b) and np.array_equal(la, lb)
