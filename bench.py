@@ -84,6 +84,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=2400,
                     help="requests of the served comparison (0 skips it); the stated workload "
                          "is 10,000 (about 42 s per mode)")
+    ap.add_argument("--realtime-seconds", type=float, default=5.0,
+                    help="length of the four-stream real-time leg at S = 16 (0 skips it)")
     ap.add_argument("--sweep", action="store_true",
                     help="only run the paper's 640-point parameter grid (S, I, rho, gamma) on a "
                          "1200x1200 frame and print it as one JSON object")
@@ -206,7 +208,9 @@ def bench_argmax_ablation(ctx, img32, mask, params, steps: int = 5):
 def bench_multiresolution(ctx, steps: int = 5):
     """Frame rates at S = 16 (B = 4, L = 6), I = 100, quarter-sampling masks,
     for the paper's real-time table resolutions (Sec. IV: VGA, SVGA, FHD,
-    UHD), plus the 1080p frame at every support size this build runs."""
+    UHD), the four frames as one batch (tuned batched launch in a graph
+    against one launch per frame), and the 1080p frame at every support size
+    this build runs."""
     import torch
 
     import paper_2202_13926_amd as fsr
@@ -215,29 +219,49 @@ def bench_multiresolution(ctx, steps: int = 5):
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
 
-    def frame_ms(h, w, B, L, seed):
-        img = synth.make_image(h, w, seed).astype(np.float32)
-        mask = synth.quarter_mask(h, w, seed + 1)
-        ti = torch.from_numpy(img).to(dev)
-        tm = torch.from_numpy(mask).to(dev)
-        o = torch.empty_like(ti)
-        p = fsr.make_params(block=B, border=L, iterations=100)
-        fsr.fsr_reconstruct(ctx, ti, tm, o, p, None, stream)
+    def timed(fn):
+        fn()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for _ in range(steps):
-            fsr.fsr_reconstruct(ctx, ti, tm, o, p, None, stream)
+            fn()
         e1.record(stream)
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / steps
 
+    def frame(h, w, seed):
+        img = synth.make_image(h, w, seed).astype(np.float32)
+        mask = synth.quarter_mask(h, w, seed + 1)
+        ti = torch.from_numpy(img).to(dev)
+        return ti, torch.from_numpy(mask).to(dev), torch.empty_like(ti)
+
+    def frame_ms(h, w, B, L, seed):
+        ti, tm, o = frame(h, w, seed)
+        p = fsr.make_params(block=B, border=L, iterations=100)
+        return timed(lambda: fsr.fsr_reconstruct(ctx, ti, tm, o, p, None, stream))
+
     res = {"workload": "synthetic frames, quarter-sampling masks, I=100, rho=0.7, gamma=0.5",
            "s16_fps": {}, "fhd_ms_by_support": {}}
-    for name, (h, w) in (("VGA 640x480", (480, 640)), ("SVGA 800x600", (600, 800)),
-                         ("FHD 1920x1080", (1080, 1920)), ("UHD 3840x2160", (2160, 3840))):
-        ms = frame_ms(h, w, 4, 6, 1700)
-        res["s16_fps"][name] = round(1e3 / ms, 2)
+    sizes = (("VGA 640x480", (480, 640)), ("SVGA 800x600", (600, 800)),
+             ("FHD 1920x1080", (1080, 1920)), ("UHD 3840x2160", (2160, 3840)))
+    for name, (h, w) in sizes:
+        res["s16_fps"][name] = round(1e3 / frame_ms(h, w, 4, 6, 1700), 2)
+
+    p16 = fsr.make_params(block=4, border=6, iterations=100)
+    items = [fsr.BatchItem(*frame(h, w, 1700), 100) for _, (h, w) in sizes]
+    best = fsr.fsr_batch_autotune(ctx, items, p16, fsr.Workspace(len(items), dev), stream)
+    graph = fsr.BatchGraph(ctx, items, p16, fsr.Workspace(len(items), dev), best)
+    graph_ms = timed(lambda: graph.launch(stream))
+    graph.close()
+    plain_ms = timed(lambda: [fsr.fsr_reconstruct(ctx, it.image, it.mask, it.out, p16, None, stream)
+                              for it in items])
+    res["s16_batch_of_four"] = {
+        "frames": "VGA + SVGA + FHD + UHD, one each",
+        "schedule": {"waves_per_group": best.waves_per_group, "chunk": best.chunk,
+                     "groups_per_cu": best.groups_per_cu},
+        "graph_ms": round(graph_ms, 4), "plain_loop_ms": round(plain_ms, 4),
+        "sets_per_s": round(1e3 / graph_ms, 2)}
     for S in (8, 16, 24, 32):
         res["fhd_ms_by_support"][f"S={S}"] = round(frame_ms(1080, 1920, 4, (S - 4) // 2, 1800), 4)
     return res
@@ -354,6 +378,110 @@ def bench_batched(ctx, steps: int = 5):
             "speedup_vs_plain_loop": round(plain_ms / min(batched_ms, graph_ms), 3)}
 
 
+def replay_trace(srv, trace, frame_of):
+    """Submits the requests of ``trace`` to ``srv`` at their arrival times
+    (``frame_of(k, request)`` gives the k-th request's pinned image and mask)
+    while a second thread waits for and releases them in submission order.
+    Returns one row per request: submit, admit, launch and done times in
+    seconds, pixels, frame height."""
+    import queue
+    import threading
+
+    q = queue.Queue()
+    rec = []
+
+    def reaper():
+        while True:
+            item = q.get()
+            if item is None:
+                return
+            t, px, h = item
+            srv.wait(t)
+            sub, adm, lau, done = srv.timing(t)
+            srv.release(t)
+            rec.append((sub, adm, lau, done, px, h))
+
+    th = threading.Thread(target=reaper)
+    th.start()
+    t0 = time.perf_counter()
+    for k, req in enumerate(trace):
+        delay = t0 + req.arrival_s - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        img, mask = frame_of(k, req)
+        q.put((srv.submit(img, mask, req.item.iterations), req.item.height * req.item.width,
+               req.item.height))
+    q.put(None)
+    th.join()
+    return np.array(rec)
+
+
+def pinned_pool(trace, per_size: int = 3):
+    """Up to ``per_size`` distinct pinned host frames per frame size of a trace."""
+    import torch
+
+    pool = {}
+    for req in trace:
+        key = (req.item.height, req.item.width)
+        if key in pool and len(pool[key]) >= per_size:
+            continue
+        img, mask = req.item.inputs()
+        pool.setdefault(key, []).append((torch.from_numpy(img.astype(np.float32)).pin_memory(),
+                                         torch.from_numpy(mask).pin_memory()))
+    return pool
+
+
+def pick(pool, k, req):
+    frames = pool[(req.item.height, req.item.width)]
+    return frames[k % len(frames)]
+
+
+def bench_realtime_s16(ctx, seconds: float = 5.0, fps: float = 60.0, budget: int = 2 << 30):
+    """The paper's real-time setting through the server: four periodic video
+    streams at ``fps`` (VGA, SVGA, FHD, UHD; quarter-sampling masks, I = 100,
+    S = 16 with B = 4, L = 6), frames uploaded from pinned host memory.  Per
+    resolution: latency (arrival to result on the device) p50 / p99 / max and
+    the frames that missed the 1 / fps deadline; continuous batching against
+    the FIFO one-frame-per-launch loop."""
+    import paper_2202_13926_amd as fsr
+    import synth
+
+    trace = synth.realtime_trace(seconds, fps)
+    pool = pinned_pool(trace)
+    params = fsr.make_params(block=4, border=6, iterations=100)
+    deadline_ms = 1e3 / fps
+    names = {480: "VGA 640x480", 600: "SVGA 800x600", 1080: "FHD 1920x1080", 2160: "UHD 3840x2160"}
+    out = {"workload": f"4 periodic streams (VGA, SVGA, FHD, UHD) at {fps:g} fps for {seconds:g} s, "
+                       "quarter-sampling masks, S=16 (B=4, L=6), I=100, host-resident frames",
+           "requests": len(trace), "deadline_ms": round(deadline_ms, 3)}
+    for name, mode, streams, max_batch in (("continuous", fsr.FSR_SERVE_CONTINUOUS, 2, 4),
+                                           ("fifo_one_frame_per_launch", fsr.FSR_SERVE_FIFO, 1, 1)):
+        cfg = fsr.make_server_config(hbm_budget=budget, max_inflight=64, max_batch=max_batch,
+                                     streams=streams, mode=mode)
+        srv = fsr.Server(ctx, params, cfg)
+        for frames in pool.values():                          # warm-up
+            t = srv.submit(frames[0][0], frames[0][1], 100)
+            srv.wait(t)
+            srv.release(t)
+        a = replay_trace(srv, trace, lambda k, req: pick(pool, k, req))
+        st = srv.stats()
+        srv.close()
+        lat = (a[:, 3] - a[:, 0]) * 1e3
+        span = a[:, 3].max() - a[:, 0].min()
+        per = {}
+        for h, label in names.items():
+            m = lat[a[:, 5] == h]
+            per[label] = {"p50_ms": round(float(np.percentile(m, 50)), 3),
+                          "p99_ms": round(float(np.percentile(m, 99)), 3),
+                          "max_ms": round(float(m.max()), 3),
+                          "missed_deadline": int((m > deadline_ms).sum()), "frames": int(m.size)}
+        out[name] = {"by_resolution": per,
+                     "throughput_mpx_s": round(float(a[:, 4].sum() / span / 1e6), 2),
+                     "frames_per_launch": round(st["completed"] / max(st["launches"], 1), 3),
+                     "gpu_busy_frac": round(st["busy_s"] / span, 3)}
+    return out
+
+
 def bench_served(ctx, n_requests: int, rate_hz: float = 240.0, budget: int = 4 << 30,
                  max_batch: int = 2):
     """Poisson stream of frames (720p:1080p:2160p = 5:3:1, I = 100, quarter or
@@ -361,23 +489,11 @@ def bench_served(ctx, n_requests: int, rate_hz: float = 240.0, budget: int = 4 <
     continuous-batching server and against the FIFO one-frame-per-launch loop.
     Frame contents come from a pinned host pool of 3 frames per size; the
     arrival times, sizes and order follow the seeded trace."""
-    import queue
-    import threading
-
-    import torch
-
     import paper_2202_13926_amd as fsr
     import synth
 
     trace = synth.serving_trace(n_requests, rate_hz)
-    pool = {}
-    for req in trace:
-        key = (req.item.height, req.item.width)
-        if key in pool and len(pool[key]) >= 3:
-            continue
-        img, mask = req.item.inputs()
-        pool.setdefault(key, []).append((torch.from_numpy(img.astype(np.float32)).pin_memory(),
-                                         torch.from_numpy(mask).pin_memory()))
+    pool = pinned_pool(trace)
     params = fsr.make_params()
     out = {"workload": f"Poisson {rate_hz:g} frames/s, {n_requests} requests, 720p:1080p:2160p = 5:3:1, "
                        "I=100, quarter or 10-50% uniform-loss masks, host-resident input frames",
@@ -394,35 +510,9 @@ def bench_served(ctx, n_requests: int, rate_hz: float = 240.0, budget: int = 4 <
             t = srv.submit(frames[0][0], frames[0][1], 100)
             srv.wait(t)
             srv.release(t)
-        q = queue.Queue()
-        rec = []
-
-        def reaper():
-            while True:
-                item = q.get()
-                if item is None:
-                    return
-                t, px = item
-                srv.wait(t)
-                sub, adm, lau, done = srv.timing(t)
-                srv.release(t)
-                rec.append((sub, adm, lau, done, px))
-
-        th = threading.Thread(target=reaper)
-        th.start()
-        t0 = time.perf_counter()
-        for k, req in enumerate(trace):
-            delay = t0 + req.arrival_s - time.perf_counter()
-            if delay > 0:
-                time.sleep(delay)
-            frames = pool[(req.item.height, req.item.width)]
-            img, mask = frames[k % len(frames)]
-            q.put((srv.submit(img, mask, 100), req.item.height * req.item.width))
-        q.put(None)
-        th.join()
+        a = replay_trace(srv, trace, lambda k, req: pick(pool, k, req))
         st = srv.stats()
         srv.close()
-        a = np.array(rec)
         lat = (a[:, 3] - a[:, 0]) * 1e3
         span = a[:, 3].max() - a[:, 0].min()
         out[name] = {"p50_ms": round(float(np.percentile(lat, 50)), 3),
@@ -533,6 +623,8 @@ def main():
         res["precision"] = bench_precision(ctx)
     if args.serve_requests > 0:
         res["served"] = bench_served(ctx, args.serve_requests, max_batch=args.serve_max_batch)
+    if args.realtime_seconds > 0:
+        res["realtime_s16"] = bench_realtime_s16(ctx, args.realtime_seconds)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(img32, mask, w, args.cpu_blocks)
     ctx.close()

@@ -85,8 +85,8 @@ enum {
  *   iterations >= 0, 0 < rho <= 1, 0 < gamma <= 1 (Sec. II), flags a
  *   combination of FSR_FLAG_*.
  * This build runs S in {8, 16, 24, 32} with block <= 8 (FSR_ERR_UNSUPPORTED
- * otherwise); the batched and served paths, FSR_DFT_SPLIT_BF16 and
- * FSR_FLAG_LDS_ARGMAX run S = 32 only.
+ * otherwise), on the one-image, batched and served paths alike;
+ * FSR_DFT_SPLIT_BF16 and FSR_FLAG_LDS_ARGMAX run S = 32 only.
  */
 typedef struct fsr_params {
     int32_t block;       /* B: target block edge in pixels                  */
@@ -168,7 +168,7 @@ typedef struct fsr_batch_schedule {
     int32_t chunk;            /* 0: one wavefront per block on a plain grid;
                                  1..64: persistent wavefronts take `chunk`
                                  consecutive blocks per pop of a global queue */
-    int32_t groups_per_cu;    /* persistent grid = compute units x this (1..16);
+    int32_t groups_per_cu;    /* persistent grid = compute units x this (1..32);
                                  ignored when chunk == 0                       */
     int32_t reserved;         /* must be 0                                     */
 } fsr_batch_schedule;
@@ -188,7 +188,8 @@ FSR_API fsr_status fsr_batched_workspace_size(int32_t n_images, size_t *bytes);
  *              once the call returns)
  *   params     block, border, rho, gamma, dft shared by all images
  *   schedule   NULL: the schedule fsr_batch_autotune chose for a batch of
- *              this size class and dft mode on this context, else a plain grid
+ *              this size class, support and dft mode on this context, else
+ *              a plain grid
  *   workspace  device memory of >= fsr_batched_workspace_size bytes; it must
  *              not be in use by another call that has not completed
  * Asynchronous on `stream`; must not be called while `stream` is being
@@ -199,10 +200,12 @@ FSR_API fsr_status fsr_reconstruct_batched(fsr_context *ctx, const fsr_image_des
                                            const fsr_batch_schedule *schedule, void *workspace,
                                            size_t workspace_bytes, void *stream);
 
-/* Times the batch under a fixed list of candidate schedules (each run
- * reconstructs the batch, so outputs are written), stores the fastest on the
- * context for this batch's size class and dft mode and returns it in *best.  Blocks the
- * host until the timing runs finish. */
+/* Times the batch under candidate schedules: a fixed list plus persistent
+ * schedules sized to the number of workgroups a compute unit holds for this
+ * support and dft mode.  Each run reconstructs the batch, so outputs are
+ * written.  Stores the fastest on the context for this batch's size class,
+ * support and dft mode and returns it in *best.  Blocks the host until the
+ * timing runs finish. */
 FSR_API fsr_status fsr_batch_autotune(fsr_context *ctx, const fsr_image_desc *descs,
                                       int32_t n_images, const fsr_params *params,
                                       void *workspace, size_t workspace_bytes, void *stream,

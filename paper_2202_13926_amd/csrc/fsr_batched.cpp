@@ -14,6 +14,7 @@ namespace {
 
 constexpr size_t kCtrlBytes = 256;                 // queue head, padded
 constexpr int64_t kMaxBlocks = int64_t(1) << 30;   // keeps the 32-bit queue head from wrapping
+constexpr int kMaxGroupsPerCu = 32;                // a compute unit holds at most 32 wavefronts
 
 size_t workspace_bytes_for(int32_t n) {
     return kCtrlBytes + ((size_t)n * sizeof(DevDesc) + 255) / 256 * 256;
@@ -32,8 +33,9 @@ fsr_status check_schedule(const fsr_batch_schedule* s) {
         return errorf(FSR_ERR_INVALID_ARG, "waves_per_group must be 1, 2 or 4 (got %d)", s->waves_per_group);
     if (s->chunk < 0 || s->chunk > 64)
         return errorf(FSR_ERR_INVALID_ARG, "chunk must lie in [0, 64] (got %d)", s->chunk);
-    if (s->chunk > 0 && (s->groups_per_cu < 1 || s->groups_per_cu > 16))
-        return errorf(FSR_ERR_INVALID_ARG, "groups_per_cu must lie in [1, 16] (got %d)", s->groups_per_cu);
+    if (s->chunk > 0 && (s->groups_per_cu < 1 || s->groups_per_cu > kMaxGroupsPerCu))
+        return errorf(FSR_ERR_INVALID_ARG, "groups_per_cu must lie in [1, %d] (got %d)", kMaxGroupsPerCu,
+                      s->groups_per_cu);
     if (s->reserved != 0) return errorf(FSR_ERR_INVALID_ARG, "schedule.reserved must be 0");
     return FSR_OK;
 }
@@ -83,13 +85,15 @@ fsr_status plan_batch(const fsr_image_desc* descs, int32_t n, const fsr_params* 
     return FSR_OK;
 }
 
-// Size class of a batch: log2 of its work and its largest iteration count.
-// Key of the tuned-schedule table: log2 of the batch's work, the DFT mode
-// (the two kernels differ in register use) and the largest iteration count.
-uint64_t size_class(const BatchPlan& plan, int32_t dft) {
+// Key of the tuned-schedule table: log2 of the batch's work, the support
+// size and the DFT mode (the kernels differ in register and LDS use) and the
+// largest iteration count.
+uint64_t size_class(const BatchPlan& plan, const fsr_params& params) {
     uint64_t w = 0;
     for (double x = plan.work; x >= 2.0; x /= 2.0) ++w;
-    return (w << 40) | ((uint64_t)(uint32_t)dft << 32) | (uint64_t)(uint32_t)plan.max_iterations;
+    const uint64_t S = (uint64_t)(params.block + 2 * params.border);
+    return (w << 48) | (S << 40) | ((uint64_t)(uint32_t)params.dft << 32) |
+           (uint64_t)(uint32_t)plan.max_iterations;
 }
 
 fsr_batch_schedule default_schedule() { return fsr_batch_schedule{1, 0, 10, 0}; }
@@ -122,8 +126,9 @@ fsr_status prepare(fsr_context* ctx, const fsr_image_desc* descs, int32_t n, con
     if ((st = check_supported(params)) != FSR_OK) return st;
     if (params->flags & FSR_FLAG_LDS_ARGMAX)
         return errorf(FSR_ERR_UNSUPPORTED, "the LDS argmax runs in fsr_reconstruct only");
-    if (params->block + 2 * params->border != kS)
-        return errorf(FSR_ERR_UNSUPPORTED, "the batched path runs support size 32 only");
+    const int S = params->block + 2 * params->border;
+    if (S != kS && params->dft != FSR_DFT_FP32)
+        return errorf(FSR_ERR_UNSUPPORTED, "support %d runs with FSR_DFT_FP32 only", S);
     if ((st = check_schedule(schedule)) != FSR_OK) return st;
     if ((st = plan_batch(descs, n, params, plan)) != FSR_OK) return st;
     if (!workspace && n > 0) return errorf(FSR_ERR_INVALID_ARG, "workspace is NULL");
@@ -136,6 +141,7 @@ fsr_status prepare(fsr_context* ctx, const fsr_image_desc* descs, int32_t n, con
     prep->launch.n_images = n;
     prep->launch.block = params->block;
     prep->launch.border = params->border;
+    prep->launch.support = S;
     prep->launch.gamma = params->gamma;
     prep->launch.dft = params->dft == FSR_DFT_SPLIT_BF16 ? 1 : 0;
     if (schedule) {
@@ -143,7 +149,7 @@ fsr_status prepare(fsr_context* ctx, const fsr_image_desc* descs, int32_t n, con
     } else {
         BatchState& bs = context_batch(ctx);
         std::lock_guard<std::mutex> lock(context_mutex(ctx));
-        auto it = bs.tuned.find(size_class(*plan, params->dft));
+        auto it = bs.tuned.find(size_class(*plan, *params));
         prep->schedule = it != bs.tuned.end() ? it->second : default_schedule();
     }
     prep->launch.chunk = prep->schedule.chunk;
@@ -222,7 +228,7 @@ fsr_status batched_enqueue(fsr_context* ctx, const fsr_image_desc* descs, int32_
     if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
     if (cap != hipStreamCaptureStatusNone)
         return errorf(FSR_ERR_UNSUPPORTED, "stream is being captured: use fsr_batch_graph_create");
-    if ((st = context_tables(ctx, kS, params->rho, &prep.launch.tab)) != FSR_OK) return st;
+    if ((st = context_tables(ctx, prep.launch.support, params->rho, &prep.launch.tab)) != FSR_OK) return st;
     if (slot_mutex) {
         std::lock_guard<std::mutex> lock(*slot_mutex);
         if ((st = upload_async(plan, workspace, stream, slot)) != FSR_OK) return st;
@@ -264,14 +270,17 @@ fsr_status fsr_batch_autotune(fsr_context* ctx, const fsr_image_desc* descs, int
                               const fsr_params* params, void* workspace, size_t workspace_bytes,
                               void* stream, fsr_batch_schedule* best) {
     if (!best) return errorf(FSR_ERR_INVALID_ARG, "best is NULL");
-    static const fsr_batch_schedule kCandidates[] = {
-        {1, 0, 10, 0}, {2, 0, 5, 0},
+    // fixed candidates, then persistent ones that fill every compute unit
+    // with as many workgroups as the kernel's registers and LDS allow
+    static const fsr_batch_schedule kFixed[] = {
+        {1, 0, 10, 0}, {2, 0, 5, 0}, {4, 0, 2, 0},
         {1, 1, 10, 0}, {1, 2, 10, 0}, {1, 4, 10, 0}, {1, 8, 10, 0}, {1, 16, 10, 0},
         {2, 2, 5, 0}, {2, 4, 5, 0}, {2, 8, 5, 0}, {1, 4, 8, 0}, {4, 4, 2, 0},
     };
+    std::vector<fsr_batch_schedule> cands(std::begin(kFixed), std::end(kFixed));
     BatchPlan plan;
     Prepared prep;
-    fsr_status st = prepare(ctx, descs, n_images, params, &kCandidates[0], workspace, workspace_bytes,
+    fsr_status st = prepare(ctx, descs, n_images, params, &cands[0], workspace, workspace_bytes,
                             &plan, &prep);
     if (st != FSR_OK) return st;
     *best = default_schedule();
@@ -279,19 +288,33 @@ fsr_status fsr_batch_autotune(fsr_context* ctx, const fsr_image_desc* descs, int
     DeviceGuard g(context_device(ctx));
     if (g.error() != hipSuccess) return hip_fail(g.error(), "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
-    if ((st = context_tables(ctx, kS, params->rho, &prep.launch.tab)) != FSR_OK) return st;
+    if ((st = context_tables(ctx, prep.launch.support, params->rho, &prep.launch.tab)) != FSR_OK) return st;
     {
         std::lock_guard<std::mutex> lock(context_batch_mutex(ctx));
         if ((st = upload_async(plan, workspace, s, &context_batch(ctx).staging)) != FSR_OK) return st;
     }
     int cus = 0;
     if ((st = cu_count(ctx, &cus)) != FSR_OK) return st;
+    for (const int wpg : {1, 2, 4}) {
+        int resident = 0;
+        hipError_t re = batched_resident_groups(prep.launch, wpg, &resident);
+        if (re != hipSuccess) return hip_fail(re, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+        resident = std::min(std::max(resident, 1), kMaxGroupsPerCu);
+        for (const int chunk : {4, 16}) {
+            const fsr_batch_schedule c{wpg, chunk, resident, 0};
+            const bool seen = std::any_of(cands.begin(), cands.end(), [&](const fsr_batch_schedule& o) {
+                return o.waves_per_group == c.waves_per_group && o.chunk == c.chunk &&
+                       o.groups_per_cu == c.groups_per_cu;
+            });
+            if (!seen) cands.push_back(c);
+        }
+    }
     hipEvent_t t0 = nullptr, t1 = nullptr;
     hipError_t e = hipEventCreate(&t0);
     if (e == hipSuccess) e = hipEventCreate(&t1);
     if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
     float best_ms = -1.0f;
-    for (const fsr_batch_schedule& cand : kCandidates) {
+    for (const fsr_batch_schedule& cand : cands) {
         Prepared p = prep;
         p.schedule = cand;
         p.launch.chunk = cand.chunk;
@@ -313,7 +336,7 @@ fsr_status fsr_batch_autotune(fsr_context* ctx, const fsr_image_desc* descs, int
     (void)hipEventDestroy(t1);
     if (st != FSR_OK) return st;
     std::lock_guard<std::mutex> lock(context_mutex(ctx));
-    context_batch(ctx).tuned[size_class(plan, params->dft)] = *best;
+    context_batch(ctx).tuned[size_class(plan, *params)] = *best;
     return FSR_OK;
 }
 
@@ -328,7 +351,7 @@ fsr_status fsr_batch_graph_create(fsr_context* ctx, const fsr_image_desc* descs,
     if (st != FSR_OK) return st;
     DeviceGuard g(context_device(ctx));
     if (g.error() != hipSuccess) return hip_fail(g.error(), "hipSetDevice");
-    if ((st = context_tables(ctx, kS, params->rho, &prep.launch.tab)) != FSR_OK) return st;
+    if ((st = context_tables(ctx, prep.launch.support, params->rho, &prep.launch.tab)) != FSR_OK) return st;
     hipError_t e;
     if (!plan.table.empty()) {
         e = hipMemcpy(static_cast<char*>(workspace) + kCtrlBytes, plan.table.data(),

@@ -3,10 +3,12 @@
 // (heaviest images first); wavefronts either take one block each (chunk 0,
 // a plain grid: fsr_batched_grid_s32) or run persistently, popping `chunk`
 // consecutive blocks at a time from a global counter until the index space
-// is exhausted (fsr_batched_s32).  Each block runs the same arithmetic as in
-// the one-image kernel, so its result does not depend on the batch it is
-// part of.
+// is exhausted (fsr_batched_s32).  Supports 8, 16 and 24 have the same two
+// forms (fsr_batched_grid_sg, fsr_batched_sg).  Each block runs the same
+// arithmetic as in the one-image kernel, so its result does not depend on the
+// batch it is part of.
 #include "fsr_block.h"
+#include "fsr_block_sg.h"
 
 namespace fsr {
 
@@ -30,30 +32,45 @@ __device__ __forceinline__ void locate(const BatchLaunch& p, int64_t g, int& img
     end = lo + 1 < p.n_images ? p.descs[lo + 1].block_begin : p.total_blocks;
 }
 
-template <int kDft, bool kPersistent>
-__device__ __forceinline__ void batch_block(const BatchLaunch& p, int64_t g, int img, float* lds) {
+__device__ __forceinline__ BlockJob batch_job(const BatchLaunch& p, int64_t g, int img) {
     const DevDesc& d = p.descs[img];
     const int64_t local = g - d.block_begin;
     BlockJob jb;
-    jb.image = d.image;
-    jb.mask = d.mask;
-    jb.out = d.out;
-    jb.log = d.argmax_log ? d.argmax_log + local * (int64_t)d.iterations : nullptr;
+    jb.image = global_ptr(d.image);
+    jb.mask = global_ptr(d.mask);
+    jb.out = global_ptr(d.out);
+    jb.log = d.argmax_log ? global_ptr(d.argmax_log) + local * (int64_t)d.iterations : nullptr;
     jb.height = d.height;
     jb.width = d.width;
     jb.stride = d.stride;
     jb.by = (int32_t)(local / d.nbx);
     jb.bx = (int32_t)(local % d.nbx);
     jb.iterations = d.iterations;
-    reconstruct_block<kDft, kArgmaxWave, kPersistent>(jb, p.block, p.border, p.gamma, p.tab, lds);
+    return jb;
+}
+
+// Block routine of support S: the S = 32 routine in its DFT mode, or the
+// smaller-support one (FP32 DFTs).
+template <int S, int kDft, bool kPersistent>
+__device__ __forceinline__ void batch_block(const BatchLaunch& p, int64_t g, int img, float* lds) {
+    if constexpr (S == kS)
+        reconstruct_block<kDft, kArgmaxWave, kPersistent>(batch_job(p, g, img), p.block, p.border,
+                                                          p.gamma, p.tab, lds);
+    else
+        reconstruct_block_sg<S, kPersistent>(batch_job(p, g, img), p.block, p.border, p.gamma, p.tab, lds);
+}
+
+template <int S>
+constexpr int lds_floats_of() {
+    if constexpr (S == kS) return kLdsFloats;
+    else return SgShape<S>::kLdsFloats;
 }
 
 // Plain grid (chunk 0): one block per wavefront, no loop, so the block
 // routine runs in its one-block form (padded planes, both spectra in
 // registers), as in the one-image kernel.
-template <int kWaves, int kDft>
-__global__ __launch_bounds__(64 * kWaves) void fsr_batched_grid_s32(BatchLaunch p) {
-    __shared__ __align__(16) float lds[kWaves * kLdsFloats];
+template <int kWaves, int S, int kDft>
+__device__ __forceinline__ void grid_body(const BatchLaunch& p, float* lds) {
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int64_t groups = (p.total_blocks + kWaves - 1) / kWaves;
     const int64_t g = xcd_contiguous(blockIdx.x, groups) * kWaves + wave;
@@ -61,18 +78,17 @@ __global__ __launch_bounds__(64 * kWaves) void fsr_batched_grid_s32(BatchLaunch 
     int img = 0;
     int64_t img_begin = 0, img_end = 0;
     locate(p, g, img, img_begin, img_end);
-    batch_block<kDft, false>(p, g, img, lds + wave * kLdsFloats);
+    batch_block<S, kDft, false>(p, g, img, lds + wave * lds_floats_of<S>());
 }
 
 // Persistent (chunk > 0): wavefronts pop `chunk` blocks at a time.
-template <int kWaves, int kDft>
-__global__ __launch_bounds__(64 * kWaves) void fsr_batched_s32(BatchLaunch p) {
-    __shared__ __align__(16) float lds[kWaves * kLdsFloats];
+template <int kWaves, int S, int kDft>
+__device__ __forceinline__ void queue_body(const BatchLaunch& p, float* lds) {
     // wave-uniform by construction; readfirstlane lets the compiler see it,
     // so block indices and descriptors stay in scalar registers
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
-    float* mine = lds + wave * kLdsFloats;
+    float* mine = lds + wave * lds_floats_of<S>();
     // [next, end): blocks this wavefront still owns; refilled from the queue
     int64_t next = 0, end = 0;
     int img = 0;
@@ -88,9 +104,33 @@ __global__ __launch_bounds__(64 * kWaves) void fsr_batched_s32(BatchLaunch p) {
             if (end > p.total_blocks) end = p.total_blocks;
         }
         locate(p, next, img, img_begin, img_end);
-        batch_block<kDft, true>(p, next, img, mine);
+        batch_block<S, kDft, true>(p, next, img, mine);
         ++next;
     }
+}
+
+template <int kWaves, int kDft>
+__global__ __launch_bounds__(64 * kWaves) void fsr_batched_grid_s32(BatchLaunch p) {
+    __shared__ __align__(16) float lds[kWaves * kLdsFloats];
+    grid_body<kWaves, kS, kDft>(p, lds);
+}
+
+template <int kWaves, int kDft>
+__global__ __launch_bounds__(64 * kWaves) void fsr_batched_s32(BatchLaunch p) {
+    __shared__ __align__(16) float lds[kWaves * kLdsFloats];
+    queue_body<kWaves, kS, kDft>(p, lds);
+}
+
+template <int kWaves, int S>
+__global__ __launch_bounds__(64 * kWaves) void fsr_batched_grid_sg(BatchLaunch p) {
+    __shared__ __align__(16) float lds[kWaves * SgShape<S>::kLdsFloats];
+    grid_body<kWaves, S, kDftFft32>(p, lds);
+}
+
+template <int kWaves, int S>
+__global__ __launch_bounds__(64 * kWaves) void fsr_batched_sg(BatchLaunch p) {
+    __shared__ __align__(16) float lds[kWaves * SgShape<S>::kLdsFloats];
+    queue_body<kWaves, S, kDftFft32>(p, lds);
 }
 
 template <int kDft>
@@ -115,6 +155,55 @@ static hipError_t launch_waves(const BatchLaunch& p, int waves_per_group, dim3 g
     return hipGetLastError();
 }
 
+template <int S>
+static hipError_t launch_waves_sg(const BatchLaunch& p, int waves_per_group, dim3 grid, dim3 block,
+                                  hipStream_t stream) {
+    const bool queue = p.chunk > 0;
+    switch (waves_per_group) {
+    case 1:
+        if (queue) hipLaunchKernelGGL((fsr_batched_sg<1, S>), grid, block, 0, stream, p);
+        else hipLaunchKernelGGL((fsr_batched_grid_sg<1, S>), grid, block, 0, stream, p);
+        break;
+    case 2:
+        if (queue) hipLaunchKernelGGL((fsr_batched_sg<2, S>), grid, block, 0, stream, p);
+        else hipLaunchKernelGGL((fsr_batched_grid_sg<2, S>), grid, block, 0, stream, p);
+        break;
+    case 4:
+        if (queue) hipLaunchKernelGGL((fsr_batched_sg<4, S>), grid, block, 0, stream, p);
+        else hipLaunchKernelGGL((fsr_batched_grid_sg<4, S>), grid, block, 0, stream, p);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename K>
+static hipError_t resident(K kernel, int waves_per_group, int* groups) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(groups, kernel, 64 * waves_per_group, 0);
+}
+
+template <int kWaves>
+static hipError_t resident_of(const BatchLaunch& p, int* groups) {
+    switch (p.support) {
+    case 8: return resident(fsr_batched_sg<kWaves, 8>, kWaves, groups);
+    case 16: return resident(fsr_batched_sg<kWaves, 16>, kWaves, groups);
+    case 24: return resident(fsr_batched_sg<kWaves, 24>, kWaves, groups);
+    case kS:
+        if (p.dft == kDftSplitBf16) return resident(fsr_batched_s32<kWaves, kDftSplitBf16>, kWaves, groups);
+        return resident(fsr_batched_s32<kWaves, kDftFft32>, kWaves, groups);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t batched_resident_groups(const BatchLaunch& p, int waves_per_group, int* groups) {
+    switch (waves_per_group) {
+    case 1: return resident_of<1>(p, groups);
+    case 2: return resident_of<2>(p, groups);
+    case 4: return resident_of<4>(p, groups);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_batched(const BatchLaunch& p, int waves_per_group, int64_t groups,
                           hipStream_t stream) {
     if (p.total_blocks <= 0) return hipSuccess;
@@ -124,6 +213,13 @@ hipError_t launch_batched(const BatchLaunch& p, int waves_per_group, int64_t gro
         groups = (p.total_blocks + waves_per_group - 1) / waves_per_group;
     }
     const dim3 grid((unsigned)groups), block(64 * waves_per_group);
+    switch (p.support) {
+    case kS: break;
+    case 8: return launch_waves_sg<8>(p, waves_per_group, grid, block, stream);
+    case 16: return launch_waves_sg<16>(p, waves_per_group, grid, block, stream);
+    case 24: return launch_waves_sg<24>(p, waves_per_group, grid, block, stream);
+    default: return hipErrorInvalidValue;
+    }
     if (p.dft == kDftSplitBf16) return launch_waves<kDftSplitBf16>(p, waves_per_group, grid, block, stream);
     return launch_waves<kDftFft32>(p, waves_per_group, grid, block, stream);
 }

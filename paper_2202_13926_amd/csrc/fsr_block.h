@@ -113,10 +113,10 @@ __device__ __forceinline__ float max_abs_and_scale(const float (&x)[16], float& 
 
 // Everything a block needs to know about its image and the method.
 struct BlockJob {
-    const float* image;
-    const uint8_t* mask;
-    float* out;
-    uint16_t* log;          // this block's I log entries, or nullptr
+    const global_t<float>* image;
+    const global_t<uint8_t>* mask;
+    global_t<float>* out;
+    global_t<uint16_t>* log;   // this block's I log entries, or nullptr
     int32_t height, width;
     int64_t stride;
     int32_t by, bx;
@@ -174,7 +174,7 @@ __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int
         const int64_t off = in ? (int64_t)y * jb.stride + x : 0;
         const uint8_t kraw = jb.mask[off];
         const float fraw = jb.image[off];
-        const float rp = tab.rho_pow[m * kS + c];
+        const float rp = global_ptr(tab.rho_pow)[m * kS + c];
         const uint8_t k = in ? kraw : (uint8_t)0;
         const float f = fraw;
         const float w = k ? rp : 0.0f;
@@ -262,7 +262,7 @@ __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int
         const float gi = w00 > 0.0f ? gamma / w00 : 0.0f;
         float wf[16];
 #pragma unroll
-        for (int s = 0; s < 16; ++s) wf[s] = tab.freq_w[(2 * s + h) * kS + c];
+        for (int s = 0; s < 16; ++s) wf[s] = global_ptr(tab.freq_w)[(2 * s + h) * kS + c];
         // lane i of tw_re/tw_im holds t32[i & 31] for the target model's phases
         const int tw_re = __float_as_int(kTw.re[c]), tw_im = __float_as_int(kTw.im[c]);
         // loop-invariant lane offsets: bpermute byte addresses of the target

@@ -116,11 +116,20 @@ __device__ __forceinline__ void dft2_sg(const float (&v)[SgShape<S>::NS], float 
     wave_sync();   // the scratch area is reused by the caller
 }
 
-template <int S>
+// kPersistent: the caller loops over blocks; as in the S = 32 routine, the
+// lane index and table pointers are made opaque so that the compiler keeps
+// no per-block constant live across the caller's loop.
+template <int S, bool kPersistent = false>
 __device__ __forceinline__ void reconstruct_block_sg(const BlockJob& jb, int B, int L, float gamma,
-                                                     const BlockTables& tab, float* lds) {
+                                                     const BlockTables& tab_in, float* lds) {
     constexpr int G = SgShape<S>::G, NS = SgShape<S>::NS, NL = SgShape<S>::NL;
-    const int lane = (int)(threadIdx.x & 63);
+    const int lane = kPersistent ? opaque((int)(threadIdx.x & 63)) : (int)(threadIdx.x & 63);
+    BlockTables tab = tab_in;
+    if constexpr (kPersistent) {
+        tab.rho_pow = opaque_ptr(tab_in.rho_pow);
+        tab.freq_w = opaque_ptr(tab_in.freq_w);
+        tab.dft_sg = opaque_ptr(tab_in.dft_sg);
+    }
     const bool active = lane < NL;
     // inactive lanes (S = 24) get an in-range (c, h) so that every LDS
     // address they form stays inside the tables
@@ -131,7 +140,11 @@ __device__ __forceinline__ void reconstruct_block_sg(const BlockJob& jb, int B, 
     float* scr = lds + 2 * S * S;
 
     // ---- DFT table into LDS (S^2 float2, the same for every block)
-    for (int i = lane; i < S * S; i += 64) ftab[i] = tab.dft_sg[i];
+    {
+        const global_t<const uint64_t>* src = global_ptr(reinterpret_cast<const uint64_t*>(tab.dft_sg));
+        uint64_t* dst = reinterpret_cast<uint64_t*>(ftab);
+        for (int i = lane; i < S * S; i += 64) dst[i] = src[i];
+    }
 
     // ---- gather and weighting: slot s holds pixel (G s + h, c)
     float xr[NS], wr[NS];
@@ -145,7 +158,7 @@ __device__ __forceinline__ void reconstruct_block_sg(const BlockJob& jb, int B, 
         const int64_t off = in ? (int64_t)y * jb.stride + x : 0;
         const uint8_t kraw = jb.mask[off];
         const float fraw = jb.image[off];
-        const float rp = tab.rho_pow[m * S + c];
+        const float rp = global_ptr(tab.rho_pow)[m * S + c];
         const uint8_t k = in ? kraw : (uint8_t)0;
         any_known |= ballot(k != 0);
         xr[s] = k ? fraw : 0.0f;
@@ -194,7 +207,7 @@ __device__ __forceinline__ void reconstruct_block_sg(const BlockJob& jb, int B, 
         const float gi = w00 > 0.0f ? gamma / w00 : 0.0f;
         float wf[NS];
 #pragma unroll
-        for (int s = 0; s < NS; ++s) wf[s] = tab.freq_w[(G * s + h) * S + c];
+        for (int s = 0; s < NS; ++s) wf[s] = global_ptr(tab.freq_w)[(G * s + h) * S + c];
         // lane i (< S) of tw_re / tw_im holds F[1][i] = exp(-j 2 pi i / S)
         const float2 tw = ftab[S + (lane % S)];
         const int tw_re = __float_as_int(tw.x), tw_im = __float_as_int(tw.y);

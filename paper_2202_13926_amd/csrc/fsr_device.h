@@ -254,6 +254,19 @@ __device__ __forceinline__ T* opaque_ptr(T* p) {
     return p;
 }
 
+// Objects in global memory (never LDS or scratch), addressed with global
+// instructions.  A pointer read from memory (a batch descriptor) is otherwise
+// generic, and the compiler then uses FLAT instructions, which also count on
+// the LDS wait counter: one FLAT store in a loop turns every LDS wait there
+// into a full drain.
+template <typename T>
+using global_t = __attribute__((address_space(1))) T;
+
+template <typename T>
+__device__ __forceinline__ global_t<T>* global_ptr(T* p) {
+    return (global_t<T>*)p;
+}
+
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 __device__ __forceinline__ float readlane_f(float v, int lane) {

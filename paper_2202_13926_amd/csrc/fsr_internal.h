@@ -74,6 +74,7 @@ struct BatchLaunch {
     int32_t n_images;
     int32_t chunk;          // blocks per queue pop; 0 = one wavefront per block, no queue
     int32_t block, border;
+    int32_t support;        // S = B + 2L: 32, or 8, 16, 24 (FP32 DFTs only)
     float gamma;
     BlockTables tab;
     int32_t dft;            // 0: FP32 FFTs, 1: split-bf16 matrix products
@@ -84,5 +85,10 @@ struct BatchLaunch {
 // (persistent mode) on `stream`.
 hipError_t launch_batched(const BatchLaunch& p, int waves_per_group, int64_t groups,
                           hipStream_t stream);
+
+// Workgroups of `waves_per_group` wavefronts that one compute unit holds at
+// once in the persistent batched kernel for p.support and p.dft (register
+// and LDS limits, from the HIP occupancy calculator).
+hipError_t batched_resident_groups(const BatchLaunch& p, int waves_per_group, int* groups);
 
 }  // namespace fsr

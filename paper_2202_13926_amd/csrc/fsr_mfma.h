@@ -118,7 +118,7 @@ __device__ __forceinline__ void dft2_real_mfma(float (&xr)[16], float (&xi)[16],
         for (int q = 0; q < 2; ++q)
 #pragma unroll
             for (int i = 0; i < kTerms; ++i)
-                f[part][q][i] = fop[((part * 2 + q) * kMfmaMaxTerms + i) * 64 + lane];
+                f[part][q][i] = global_ptr(fop)[((part * 2 + q) * kMfmaMaxTerms + i) * 64 + lane];
     bf16x8 x[2][kTerms];
     split8(xr, x[0]);
     split8(xr + 8, x[1]);

@@ -7,10 +7,10 @@ namespace fsr {
 __device__ __forceinline__ BlockJob plain_job(const PlainLaunch& p, int64_t blk) {
     const ImageDesc& im = p.img;
     BlockJob jb;
-    jb.image = im.image;
-    jb.mask = im.mask;
-    jb.out = im.out;
-    jb.log = im.argmax_log ? im.argmax_log + blk * (int64_t)im.iterations : nullptr;
+    jb.image = global_ptr(im.image);
+    jb.mask = global_ptr(im.mask);
+    jb.out = global_ptr(im.out);
+    jb.log = im.argmax_log ? global_ptr(im.argmax_log) + blk * (int64_t)im.iterations : nullptr;
     jb.height = im.height;
     jb.width = im.width;
     jb.stride = im.stride;

@@ -406,8 +406,9 @@ fsr_status fsr_server_create(fsr_context* ctx, const fsr_params* params, const f
     if ((st = check_supported(params)) != FSR_OK) return st;
     if (params->flags & FSR_FLAG_LDS_ARGMAX)
         return errorf(FSR_ERR_UNSUPPORTED, "the LDS argmax runs in fsr_reconstruct only");
-    if (params->block + 2 * params->border != kS)
-        return errorf(FSR_ERR_UNSUPPORTED, "the server runs support size 32 only");
+    const int S = params->block + 2 * params->border;
+    if (S != kS && params->dft != FSR_DFT_FP32)
+        return errorf(FSR_ERR_UNSUPPORTED, "support %d runs with FSR_DFT_FP32 only", S);
     if ((st = check_config(cfg)) != FSR_OK) return st;
     fsr_server* s = new (std::nothrow) fsr_server();
     if (!s) return errorf(FSR_ERR_OUT_OF_MEMORY, "server allocation failed");
@@ -435,7 +436,7 @@ fsr_status fsr_server_create(fsr_context* ctx, const fsr_params* params, const f
         return errorf(FSR_ERR_HIP, "server streams or workspace: %s", hipGetErrorString(e));
     }
     BlockTables tab;
-    if ((st = context_tables(ctx, kS, params->rho, &tab)) != FSR_OK) {   // build tables before serving
+    if ((st = context_tables(ctx, S, params->rho, &tab)) != FSR_OK) {   // build tables before serving
         free_resources(s);
         delete s;
         return st;

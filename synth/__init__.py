@@ -215,3 +215,23 @@ def serving_trace(n: int = 10000, rate_hz: float = 240.0, seed: int = 1400,
             mask = f"uniform:{rng.uniform(0.1, 0.5):.4f}"
         reqs.append(Request(float(t[i]), BatchItem(int(h), int(w), mask, iterations, seed + 1 + 2 * i)))
     return reqs
+
+
+_REALTIME_SIZES = ((480, 640), (600, 800), (1080, 1920), (2160, 3840))
+
+
+def realtime_trace(seconds: float = 5.0, fps: float = 30.0, sizes=_REALTIME_SIZES,
+                   seed: int = 1500, iterations: int = 100) -> list[Request]:
+    """One periodic video stream per frame size, each at ``fps`` frames per
+    second for ``seconds``, with quarter-sampling masks; stream k starts at
+    the phase k / (len(sizes) * fps), so arrivals interleave.  Requests are
+    returned in arrival order."""
+    reqs = []
+    n = int(round(seconds * fps))
+    for k, (h, w) in enumerate(sizes):
+        phase = k / (len(sizes) * fps)
+        for i in range(n):
+            reqs.append(Request(phase + i / fps,
+                                BatchItem(int(h), int(w), "quarter", iterations, seed + 100 * k + 2 * (i % 3))))
+    reqs.sort(key=lambda r: r.arrival_s)
+    return reqs

@@ -116,10 +116,12 @@ def test_batched_validates_before_touching_the_device(lib):
     assert call([alias], 1) == E                                       # out overlaps image
     assert call([good], 1, ws_bytes=100) == E                          # workspace too small
     assert call([good], 1, ws=None) == E
-    for s in (fsr.make_schedule(3, 0, 10), fsr.make_schedule(1, 65, 10), fsr.make_schedule(1, 4, 0),
+    for s in (fsr.make_schedule(3, 0, 10), fsr.make_schedule(1, 65, 10), fsr.make_schedule(1, 4, 0), fsr.make_schedule(1, 4, 33),
               binding.fsr_batch_schedule(1, 0, 10, 7)):
         assert call([good], 1, sched=s) == E
-    assert call([good], 1, params=fsr.make_params(block=4, border=6)) == binding.FSR_ERR_UNSUPPORTED
+    assert call([good], 1, params=fsr.make_params(block=4, border=4)) == binding.FSR_ERR_UNSUPPORTED
+    assert call([good], 1, params=fsr.make_params(block=4, border=6, dft=fsr.FSR_DFT_SPLIT_BF16)) == \
+        binding.FSR_ERR_UNSUPPORTED
     assert call([good], 1, params=fsr.make_params(flags=fsr.FSR_FLAG_LDS_ARGMAX)) == binding.FSR_ERR_UNSUPPORTED
     assert lib.fsr_last_error_message().decode()
     out = ctypes.c_void_p()
@@ -145,8 +147,9 @@ def test_server_config_validated_before_touching_the_device(lib):
         assert lib.fsr_server_create(fake_ctx, ctypes.byref(p), ctypes.byref(c), ctypes.byref(out)) == E
     c = binding.make_server_config()
     assert lib.fsr_server_create(None, ctypes.byref(p), ctypes.byref(c), ctypes.byref(out)) == E
-    assert lib.fsr_server_create(fake_ctx, ctypes.byref(fsr.make_params(block=4, border=6)),
-                                 ctypes.byref(c), ctypes.byref(out)) == binding.FSR_ERR_UNSUPPORTED
+    for other in (fsr.make_params(block=4, border=4), fsr.make_params(block=4, border=6, dft=fsr.FSR_DFT_SPLIT_BF16)):
+        assert lib.fsr_server_create(fake_ctx, ctypes.byref(other), ctypes.byref(c),
+                                     ctypes.byref(out)) == binding.FSR_ERR_UNSUPPORTED
     assert lib.fsr_server_create(fake_ctx, ctypes.byref(fsr.make_params(flags=fsr.FSR_FLAG_LDS_ARGMAX)),
                                  ctypes.byref(c), ctypes.byref(out)) == binding.FSR_ERR_UNSUPPORTED
     t = ctypes.c_uint64()

@@ -66,3 +66,15 @@ def test_batch_and_trace_are_seeded_and_mixed():
     sizes = [r.item.height for r in tr]
     frac720 = sizes.count(720) / len(sizes)
     assert abs(frac720 - 5 / 9) < 0.05
+
+
+def test_realtime_trace_interleaves_periodic_streams():
+    tr = synth.realtime_trace(2.0, 30.0)
+    assert len(tr) == 4 * 60
+    t = np.array([r.arrival_s for r in tr])
+    assert np.all(np.diff(t) > 0)                       # distinct phases: no two arrivals coincide
+    for h in (480, 600, 1080, 2160):
+        ts = np.array([r.arrival_s for r in tr if r.item.height == h])
+        assert len(ts) == 60 and np.allclose(np.diff(ts), 1 / 30.0)
+    assert {r.item.mask for r in tr} == {"quarter"}
+    assert [r.item.seed for r in tr] == [r.item.seed for r in synth.realtime_trace(2.0, 30.0)]
