@@ -16,8 +16,9 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libfsr.so")
 
-SOURCES = ["fsr_api.cpp", "fsr_batched.cpp", "fsr_serve.cpp", "fsr_plain.hip", "fsr_batched.hip"]
-HEADERS = ["fsr_device.h", "fsr_block.h", "fsr_internal.h", "fsr_runtime.h"]
+SOURCES = ["fsr_api.cpp", "fsr_batched.cpp", "fsr_serve.cpp", "fsr_plain.hip", "fsr_plain_sg.hip",
+           "fsr_batched.hip"]
+HEADERS = ["fsr_device.h", "fsr_block.h", "fsr_block_sg.h", "fsr_mfma.h", "fsr_internal.h", "fsr_runtime.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

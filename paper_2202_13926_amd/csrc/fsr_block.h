@@ -123,6 +123,23 @@ struct BlockJob {
     int32_t iterations;
 };
 
+// Block `blk` of a one-image launch.
+__device__ __forceinline__ BlockJob plain_job(const PlainLaunch& p, int64_t blk) {
+    const ImageDesc& im = p.img;
+    BlockJob jb;
+    jb.image = global_ptr(im.image);
+    jb.mask = global_ptr(im.mask);
+    jb.out = global_ptr(im.out);
+    jb.log = im.argmax_log ? global_ptr(im.argmax_log) + blk * (int64_t)im.iterations : nullptr;
+    jb.height = im.height;
+    jb.width = im.width;
+    jb.stride = im.stride;
+    jb.by = (int32_t)(blk / im.nbx);
+    jb.bx = (int32_t)(blk % im.nbx);
+    jb.iterations = im.iterations;
+    return jb;
+}
+
 // kDft selects the forward transforms: kDftFft32 (FP32 FFTs on the vector
 // ALUs) or kDftSplitBf16 (split-bf16 products on the matrix cores).
 constexpr int kDftFft32 = 0;

@@ -51,6 +51,7 @@ struct PlainLaunch {
 };
 
 hipError_t launch_plain(const PlainLaunch& p, hipStream_t stream);
+hipError_t launch_plain_sg(const PlainLaunch& p, hipStream_t stream);   // S = 8, 16, 24
 
 // Device-side descriptor of one image of a batch (64 bytes).  Images are
 // stored in queue order; block_begin is the prefix sum of block counts.
