@@ -15,21 +15,32 @@
 // of a real tile is bitwise Hermitian without a symmetrisation step (the
 // rounding of a negated operand is the negated rounding).
 //
-// LDS per wavefront, 6 S^2 floats: the DFT table (S^2 float2), then a
-// scratch area that holds the tile and the first pass of the DFT, and
-// afterwards W with duplicated rows (2S x S float2).
+// LDS per wavefront: during the transforms the DFT table (S^2 float2) and
+// a scratch area for the tile and the first pass of the DFT (6 S^2 floats);
+// during the iterations W with duplicated rows, and for S <= kFullDupMax
+// duplicated columns too (2S x 2S float2, entry (R, C) = W[R mod S][C mod S],
+// 8 S^2 floats), so that the cyclic shift of Eqs. 14-15 is one uniform
+// offset added to a per-lane address; above that the column wraps per lane.
 #pragma once
 
 #include "fsr_block.h"
 
 namespace fsr {
 
+// Largest support whose W table also duplicates its columns.  Measured: at
+// S = 16 the 2S x 2S table (8 KiB) costs more in resident wavefronts than
+// the column wrap it saves (1080p, I = 100: 1.28 against 1.25 ms); at S = 8
+// it costs nothing (2 KiB).
+constexpr int kFullDupMax = 8;
+
 template <int S>
 struct SgShape {
     static constexpr int G = 64 / S;          // lane groups
     static constexpr int NS = S / G;          // slots per lane
     static constexpr int NL = G * S;          // active lanes
-    static constexpr int kLdsFloats = 6 * S * S;
+    static constexpr bool kFullDup = S <= kFullDupMax;   // columns duplicated too
+    static constexpr int P = kFullDup ? 2 * S : S;        // W table pitch, float2
+    static constexpr int kLdsFloats = kFullDup ? 8 * S * S : 6 * S * S;
     static constexpr uint32_t kModMagic = (65536u + S - 1) / S;
     static_assert(S % 2 == 0 && S >= 8 && S < 32 && S % G == 0, "even S in [8, 32)");
     static_assert(NS <= 16, "slot code fits in 4 bits");
@@ -50,7 +61,9 @@ __device__ __forceinline__ int mod_small(int q) {
         return q & (S - 1);
     } else {
         static_assert(mod_magic_exact<S>(), "division by multiply-shift must be exact");
-        return q - S * (int)(((uint32_t)q * SgShape<S>::kModMagic) >> 16);
+        // q < 2 S^2 and the magic number are below 2^12 and 2^16: the
+        // product fits the full-rate 24-bit multiplier
+        return q - S * (int)((uint32_t)mul_u24((int)SgShape<S>::kModMagic, q) >> 16);
     }
 }
 
@@ -165,8 +178,10 @@ __device__ __forceinline__ void reconstruct_block_sg(const BlockJob& jb, int B, 
         wr[s] = k ? rp : 0.0f;
     }
 
-    // ---- target pixel owned by this lane (lanes 0 .. B*B-1)
-    const int ti = lane / B, tj = lane - (lane / B) * B;
+    // ---- target pixel owned by this lane (lanes 0 .. B*B-1; the other
+    // lanes model pixel (L, L) and discard it)
+    const bool owner = lane < B * B;
+    const int ti = owner ? lane / B : 0, tj = owner ? lane - (lane / B) * B : 0;
     const int tm = L + ti, tn = L + tj;
     float acc = 0.0f;
     const int iters = jb.iterations;
@@ -193,24 +208,39 @@ __device__ __forceinline__ void reconstruct_block_sg(const BlockJob& jb, int B, 
             xr[s] = fmaf(mu, wr[s], xr[s]);
             xi[s] = fmaf(mu, wi[s], xi[s]);
         }
-        // W with duplicated rows: row r holds W[r mod S]
-        float2* wtab = reinterpret_cast<float2*>(scr);
-        if (active) {
-#pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                const int k = G * s + h;
-                wtab[k * S + c] = make_float2(wr[s], wi[s]);
-                wtab[(k + S) * S + c] = make_float2(wr[s], wi[s]);
-            }
-        }
         const float w00 = readlane_f(wr[0], 0);
         const float gi = w00 > 0.0f ? gamma / w00 : 0.0f;
         float wf[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) wf[s] = global_ptr(tab.freq_w)[(G * s + h) * S + c];
-        // lane i (< S) of tw_re / tw_im holds F[1][i] = exp(-j 2 pi i / S)
+        // lane i (< S) of tw_re / tw_im holds F[1][i] = exp(-j 2 pi i / S),
+        // read before W overwrites the table
         const float2 tw = ftab[S + (lane % S)];
         const int tw_re = __float_as_int(tw.x), tw_im = __float_as_int(tw.y);
+        wave_sync();
+        // W with duplicated rows (and columns when kFullDup): entry (R, C)
+        // holds W[R mod S][C mod S]
+        constexpr int P = SgShape<S>::P;   // table pitch in float2
+        constexpr bool kFullDup = SgShape<S>::kFullDup;
+        float2* wtab = reinterpret_cast<float2*>(lds);
+        if (active) {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const int k = G * s + h;
+                const float2 wv = make_float2(wr[s], wi[s]);
+                wtab[k * P + c] = wv;
+                wtab[(k + S) * P + c] = wv;
+                if constexpr (kFullDup) {
+                    wtab[k * P + c + S] = wv;
+                    wtab[(k + S) * P + c + S] = wv;
+                }
+            }
+        }
+        // lane constants kept as computed here (the compiler would otherwise
+        // re-derive them inside the loop)
+        const int lbase = opaque(8 * (h * P + (kFullDup ? c : 0)));   // entry (h, c), or row h
+        const int tm4 = opaque(4 * tm), tn4 = opaque(4 * tn);
+        const char* wbytes = reinterpret_cast<const char*>(wtab);
         wave_sync();
 
         for (int it = 0; it < iters; ++it) {
@@ -234,22 +264,31 @@ __device__ __forceinline__ void reconstruct_block_sg(const BlockJob& jb, int B, 
             const float cr = gi * pr, ci = gi * pim;    // gamma * p (Eqs. 10-11)
             if (jb.log != nullptr && lane == 0) jb.log[it] = (uint16_t)idx;
 
-            // model: g += gamma p exp(+j 2 pi (u m + v n) / S) on the target
-            const int q = mod_small<S>(u * tm + v * tn);
-            const float er = __int_as_float(__builtin_amdgcn_ds_bpermute(4 * q, tw_re));
-            const float ei = __int_as_float(__builtin_amdgcn_ds_bpermute(4 * q, tw_im));
+            // model: g += gamma p exp(+j 2 pi (u m + v n) / S) on the target;
+            // the phase index on the 24-bit multiplier
+            int q4;
+            if constexpr ((S & (S - 1)) == 0) q4 = mad_u24(u, tm4, mul_u24(v, tn4)) & (4 * S - 1);
+            else q4 = 4 * mod_small<S>(mad_u24(u, tm, mul_u24(v, tn)));
+            const float er = __int_as_float(__builtin_amdgcn_ds_bpermute(q4, tw_re));
+            const float ei = __int_as_float(__builtin_amdgcn_ds_bpermute(q4, tw_im));
             acc = fmaf(cr, er, acc);
             acc = fmaf(ci, ei, acc);
 
-            // residual (Eqs. 12, 14-15): slot s reads duplicated row
-            // (h - u) mod S + G s, column (c - v) mod S
-            int r0 = h - u, col = c - v;
-            r0 += r0 < 0 ? S : 0;
-            col += col < 0 ? S : 0;
-            const float2* wrow = wtab + (r0 * S + col);
+            // residual (Eqs. 12, 14-15): bin (G s + h, c) reads entry
+            // (G s + h - u + S, c - v + S), i.e. this lane's entry (h, c)
+            // moved by a uniform offset, plus G rows per slot; without
+            // duplicated columns the column (c - v) mod S wraps per lane
+            const float2* wrow;
+            if constexpr (kFullDup) {
+                wrow = reinterpret_cast<const float2*>(wbytes + lbase + 8 * ((S - u) * P + (S - v)));
+            } else {
+                int col = c - v;
+                col += col < 0 ? S : 0;
+                wrow = reinterpret_cast<const float2*>(wbytes + lbase + 8 * ((S - u) * P + col));
+            }
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
-                const float2 w = wrow[G * S * s];
+                const float2 w = wrow[G * P * s];
                 xr[s] = fmaf(-cr, w.x, xr[s]);
                 xr[s] = fmaf(ci, w.y, xr[s]);
                 xi[s] = fmaf(-cr, w.y, xi[s]);
@@ -262,7 +301,7 @@ __device__ __forceinline__ void reconstruct_block_sg(const BlockJob& jb, int B, 
     }
 
     // ---- compose (Sec. II): known pixels copied, unknown pixels Re g
-    if (lane < B * B) {
+    if (owner) {
         const int y = jb.by * B + ti, xx = jb.bx * B + tj;
         if (y < jb.height && xx < jb.width) {
             const int64_t off = (int64_t)y * jb.stride + xx;
