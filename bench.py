@@ -121,9 +121,18 @@ def cpu_baseline(img32, mask, w, n_blocks_sample):
     px = len(ids) * w.block * w.block
     what = (f"all {len(ids)} blocks of the frame" if len(ids) == w.n_blocks
             else f"{len(ids)} seeded random blocks of the same frame")
+    # one thread on a smaller seeded sample of the same blocks
+    ids1 = ids[rng.choice(len(ids), size=min(4000, len(ids)), replace=False)]
+    ids1.sort()
+    t0 = time.perf_counter()
+    oracle.reconstruct_blocks(img64, mask, ids1, w.iterations, threads=1)
+    dt1 = time.perf_counter() - t0
+    px1 = len(ids1) * w.block * w.block
     return {"value": px / dt / 1e6, "unit": "Mpixel/s", "cores": threads, "kind": "oracle",
             "sample": f"{what} ({px} pixels), FP64 C oracle, OpenMP over blocks on {threads} "
-                      f"threads, {dt:.2f} s wall"}
+                      f"threads, {dt:.2f} s wall",
+            "single_thread": {"value": px1 / dt1 / 1e6, "unit": "Mpixel/s", "cores": 1,
+                              "sample": f"{len(ids1)} of those blocks ({px1} pixels), {dt1:.2f} s wall"}}
 
 
 def bench_precision(ctx, steps: int = 3):
