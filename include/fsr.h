@@ -141,7 +141,10 @@ FSR_API fsr_status fsr_context_destroy(fsr_context *ctx);
  *   argmax_log   NULL, or N x I uint16 (N = fsr_num_blocks): the bin
  *                u*S + v chosen by each block at each iteration, block-major;
  *                0xFFFF for every iteration of a block without known pixels.
- * Asynchronous on `stream`.
+ * Asynchronous on `stream`.  The call may be captured into a HIP graph once
+ * the context holds the tables of this support and rho (built by the first
+ * call with them); under capture a missing table is FSR_ERR_UNSUPPORTED and
+ * nothing is recorded.
  */
 FSR_API fsr_status fsr_reconstruct(fsr_context *ctx, const float *image, const uint8_t *mask,
                            float *out, int32_t height, int32_t width, int64_t stride,

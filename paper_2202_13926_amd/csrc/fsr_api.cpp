@@ -246,10 +246,17 @@ struct fsr_context {
 
 namespace fsr {
 
-// Uploads a host table once; `slot` caches the device copy.
-template <typename T>
-static fsr_status upload_table(const std::vector<T>& h, T** slot, const char* what) {
+// Uploads a host table once; `slot` caches the device copy and `make` builds
+// the host values only when the table is missing.  With may_build false a
+// missing table is an error and no HIP call is made (stream capture).
+template <typename T, typename Make>
+static fsr_status device_table(T** slot, bool may_build, const char* what, int S, float rho, Make make) {
     if (*slot) return FSR_OK;
+    if (!may_build)
+        return fail(FSR_ERR_UNSUPPORTED,
+                    "%s for support %d and rho %g is not on the context yet: make one call with these "
+                    "parameters outside stream capture first", what, S, (double)rho);
+    const std::vector<T> h = make();
     T* d = nullptr;
     hipError_t e = hipMalloc(&d, h.size() * sizeof(T));
     if (e != hipSuccess) return fail(FSR_ERR_OUT_OF_MEMORY, "hipMalloc(%s): %s", what, hipGetErrorString(e));
@@ -262,24 +269,29 @@ static fsr_status upload_table(const std::vector<T>& h, T** slot, const char* wh
     return FSR_OK;
 }
 
-fsr_status context_tables(fsr_context* ctx, int S, float rho, BlockTables* out) {
+fsr_status context_tables(fsr_context* ctx, int S, float rho, BlockTables* out, bool may_build) {
     std::lock_guard<std::mutex> lock(ctx->mu);
     fsr_status st;
     *out = BlockTables{};
-    if ((st = upload_table(host_freq_w(S), &ctx->freq_w[S], "frequency table")) != FSR_OK) return st;
+    if ((st = device_table(&ctx->freq_w[S], may_build, "frequency table", S, rho,
+                           [&] { return host_freq_w(S); })) != FSR_OK)
+        return st;
     if (S == kS) {
-        if (!ctx->mfma_tab) {
+        st = device_table(&ctx->mfma_tab, may_build, "dft table", S, rho, [] {
             std::vector<uint16_t> t;
             dft_table(t);
-            if ((st = upload_table(t, &ctx->mfma_tab, "dft table")) != FSR_OK) return st;
-        }
-    } else if ((st = upload_table(host_dft_sg(S), &ctx->dft_sg[S], "dft table")) != FSR_OK) {
-        return st;
+            return t;
+        });
+    } else {
+        st = device_table(&ctx->dft_sg[S], may_build, "dft table", S, rho, [&] { return host_dft_sg(S); });
     }
+    if (st != FSR_OK) return st;
     uint32_t bits;
     std::memcpy(&bits, &rho, sizeof bits);
     const uint64_t key = ((uint64_t)(uint32_t)S << 32) | bits;
-    if ((st = upload_table(host_rho_pow(S, rho), &ctx->rho_pow[key], "weight table")) != FSR_OK) return st;
+    if ((st = device_table(&ctx->rho_pow[key], may_build, "weight table", S, rho,
+                           [&] { return host_rho_pow(S, rho); })) != FSR_OK)
+        return st;
     out->rho_pow = ctx->rho_pow[key];
     out->freq_w = ctx->freq_w[S];
     out->mfma_dft = S == kS ? ctx->mfma_tab : nullptr;
@@ -383,8 +395,14 @@ fsr_status fsr_reconstruct(fsr_context* ctx, const float* image, const uint8_t* 
 
     DeviceGuard g(ctx->device);
     if (g.error() != hipSuccess) return hip_fail(g.error(), "hipSetDevice");
+    // under stream capture only a kernel launch may be recorded: the tables
+    // must already be on the context
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    hipError_t ce = hipStreamIsCapturing((hipStream_t)stream, &cap);
+    if (ce != hipSuccess) return hip_fail(ce, "hipStreamIsCapturing");
     PlainLaunch p{};
-    if ((st = context_tables(ctx, S, params->rho, &p.tab)) != FSR_OK) return st;
+    if ((st = context_tables(ctx, S, params->rho, &p.tab, cap == hipStreamCaptureStatusNone)) != FSR_OK)
+        return st;
     p.img.image = image;
     p.img.mask = mask;
     p.img.out = out;

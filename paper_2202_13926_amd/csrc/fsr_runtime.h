@@ -65,7 +65,7 @@ fsr_status validate_params(const fsr_params* p);
 fsr_status check_supported(const fsr_params* p);
 fsr_status validate_image(const float* image, const uint8_t* mask, const float* out, int32_t height,
                           int32_t width, int64_t stride, int32_t block);
-fsr_status context_tables(fsr_context* ctx, int S, float rho, BlockTables* out);
+fsr_status context_tables(fsr_context* ctx, int S, float rho, BlockTables* out, bool may_build = true);
 int context_device(const fsr_context* ctx);
 BatchState& context_batch(fsr_context* ctx);
 std::mutex& context_mutex(fsr_context* ctx);

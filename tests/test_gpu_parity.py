@@ -21,6 +21,7 @@ from synth.metrics import parity_report
 
 torch = pytest.importorskip("torch")
 import paper_2202_13926_amd as fsr  # noqa: E402
+from paper_2202_13926_amd import binding  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -363,3 +364,55 @@ def test_concurrent_contexts_and_streams(ctx):
     assert not errors, errors
     for (a, la), (b, lb) in zip(alone, results):
         assert np.array_equal(a, b) and np.array_equal(la, lb)
+
+
+@pytest.mark.filterwarnings("ignore:The CUDA Graph is empty")   # the refused call records nothing
+@pytest.mark.parametrize("B,L", [(4, 14), (4, 6)])
+def test_plain_launch_replays_in_a_graph(ctx, B, L):
+    """fsr_reconstruct captured into a graph: every replay, with eager work
+    in between and with new frame contents in the same buffers, equals the
+    eager call; under capture a table the context lacks is refused without
+    breaking the capture."""
+    announce(f"graph capture of the one-image launch, B={B} L={L}")
+    img = synth.make_image(150, 200, 1601).astype(np.float32)
+    mask = synth.make_mask("quarter", 150, 200, 1602)
+    p = fsr.make_params(block=B, border=L, iterations=80)
+    ref, ref_log = run_gpu(ctx, img, mask, p)              # eager; builds the tables
+    ti, tm = to_dev(img, mask)
+    out = torch.full_like(ti, -1.0)
+    n = fsr.fsr_num_blocks(150, 200, B)
+    log = torch.full((n, p.iterations), -1, dtype=torch.int16, device=ti.device)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fsr.fsr_reconstruct(ctx, ti, tm, out, p, log)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fsr.fsr_reconstruct(ctx, ti, tm, out, p, log)
+    other = synth.make_image(64, 64, 1603).astype(np.float32)
+    other_mask = synth.make_mask("uniform:0.4", 64, 64, 1604)
+    for _ in range(3):
+        out.fill_(-5.0)
+        log.fill_(-3)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), ref)
+        assert np.array_equal(log.cpu().numpy().view(np.uint16), ref_log)
+        run_gpu(ctx, other, other_mask, p)                 # eager work between replays
+    flipped, flipped_mask = img[::-1, ::-1].copy(), mask[::-1, ::-1].copy()
+    ti.copy_(torch.from_numpy(flipped))
+    tm.copy_(torch.from_numpy(flipped_mask))
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), run_gpu(ctx, flipped, flipped_mask, p)[0])
+    # rho 0.71 has no weight table on this context yet
+    g2 = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g2):
+        with pytest.raises(fsr.FsrError) as err:
+            fsr.fsr_reconstruct(ctx, ti, tm, out, fsr.make_params(block=B, border=L, rho=0.71), None)
+    assert err.value.status == binding.FSR_ERR_UNSUPPORTED
+    run_gpu(ctx, img, mask, p)                             # the device is still usable
