@@ -1,6 +1,9 @@
-// fsr_plain_sg.hip -- one-image FSR at supports 8, 16 and 24
-// (fsr_block_sg.h): one workgroup of one wavefront per block.
+// fsr_plain_sg.hip -- one-image FSR at supports 8, 16 and 24: one workgroup
+// of one wavefront per block (fsr_block_sg.h), or at S = 8 with B <= 4 eight
+// blocks per wavefront (fsr_block_multi.h); both give bitwise the same
+// result.
 #include "fsr_block.h"
+#include "fsr_block_multi.h"
 #include "fsr_block_sg.h"
 
 namespace fsr {
@@ -12,9 +15,26 @@ __global__ __launch_bounds__(64) void fsr_plain_sg(PlainLaunch p) {
     reconstruct_block_sg<S>(plain_job(p, blk), p.block, p.border, p.gamma, p.tab, lds);
 }
 
+template <int S, int T>
+__global__ __launch_bounds__(64) void fsr_plain_multi(PlainLaunch p) {
+    __shared__ __align__(16) float lds[MultiShape<S, T>::kLdsFloats];
+    const int64_t waves = (p.n_blocks + MultiShape<S, T>::NB - 1) / MultiShape<S, T>::NB;
+    reconstruct_multi<S, T>(p, xcd_contiguous(blockIdx.x, waves), lds);
+}
+
+template <int S, int T>
+static hipError_t launch_multi(const PlainLaunch& p, hipStream_t stream) {
+    const int64_t waves = (p.n_blocks + MultiShape<S, T>::NB - 1) / MultiShape<S, T>::NB;
+    hipLaunchKernelGGL((fsr_plain_multi<S, T>), dim3((unsigned)waves), dim3(64), 0, stream, p);
+    return hipGetLastError();
+}
+
 // The host API admits FP32 DFTs and no flags at these supports.
 hipError_t launch_plain_sg(const PlainLaunch& p, hipStream_t stream) {
     if (p.n_blocks <= 0) return hipSuccess;
+    const int bb = p.block * p.block;   // target pixels per block
+    if (p.support == 8 && bb <= 8) return launch_multi<8, 1>(p, stream);
+    if (p.support == 8 && bb <= 16) return launch_multi<8, 2>(p, stream);
     const dim3 grid((unsigned)p.n_blocks), block(64);
     switch (p.support) {
     case 8: hipLaunchKernelGGL(fsr_plain_sg<8>, grid, block, 0, stream, p); break;

@@ -18,8 +18,10 @@ import paper_2202_13926_amd as fsr  # noqa: E402
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda:0"
-# (B, L): S = 8, 16 (B = 4 and B = 8) and 24
-SPLITS = [(4, 2), (4, 6), (8, 4), (4, 10)]
+# (B, L): S = 8 (B = 2 and 4: the one-image path runs eight blocks per
+# wavefront there, so this also checks it bitwise against the one-block
+# routine), 16 (B = 4 and 8) and 24
+SPLITS = [(4, 2), (2, 3), (4, 6), (8, 4), (4, 10)]
 SCHEDULES = [fsr.make_schedule(1, 0, 10), fsr.make_schedule(4, 0, 2), fsr.make_schedule(1, 4, 10),
              fsr.make_schedule(2, 8, 5), fsr.make_schedule(4, 1, 2)]
 
