@@ -36,18 +36,24 @@ def algorithmic_flops_per_block(S: int, B: int, iters: int) -> float:
     return 12.0 * S * S * iters + 5.0 * S * S * math.log2(S * S) + 4.0 * B * B * iters
 
 
+# what the code of fsr_plain_s32 is built from: its sources and the compiler
+# flags (not the rest of the build script)
 KERNEL_SOURCES = ("paper_2202_13926_amd/csrc/fsr_block.h", "paper_2202_13926_amd/csrc/fsr_device.h",
                   "paper_2202_13926_amd/csrc/fsr_mfma.h", "paper_2202_13926_amd/csrc/fsr_plain.hip",
-                  "paper_2202_13926_amd/csrc/fsr_internal.h", "paper_2202_13926_amd/build.py")
+                  "paper_2202_13926_amd/csrc/fsr_internal.h")
 PMC_SUMMARY = "profiles/fsr_plain_s32_fhd_quarter_pmc.md"
 
 
 def kernel_hash() -> str:
     import hashlib
+
+    from paper_2202_13926_amd import build
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
+    flags = [f for f in build.FLAGS if not f.startswith(ROOT)]   # include paths vary by checkout
+    h.update(" ".join(flags).encode())
     return h.hexdigest()[:16]
 
 
