@@ -16,7 +16,8 @@
 // rounding of a negated operand is the negated rounding).
 //
 // LDS per wavefront: during the transforms the DFT table (S^2 float2) and
-// a scratch area for the tile and the first pass of the DFT (6 S^2 floats);
+// a scratch area for the tile and then, over it, the first pass of the DFT
+// (4 S^2 floats);
 // during the iterations W with duplicated rows, and for S <= kFullDupMax
 // duplicated columns too (2S x 2S float2, entry (R, C) = W[R mod S][C mod S],
 // 8 S^2 floats), so that the cyclic shift of Eqs. 14-15 is one uniform
@@ -40,7 +41,7 @@ struct SgShape {
     static constexpr int NL = G * S;          // active lanes
     static constexpr bool kFullDup = S <= kFullDupMax;   // columns duplicated too
     static constexpr int P = kFullDup ? 2 * S : S;        // W table pitch, float2
-    static constexpr int kLdsFloats = kFullDup ? 8 * S * S : 6 * S * S;
+    static constexpr int kLdsFloats = kFullDup ? 8 * S * S : 4 * S * S;
     static constexpr uint32_t kModMagic = (65536u + S - 1) / S;
     static_assert(S % 2 == 0 && S >= 8 && S < 32 && S % G == 0, "even S in [8, 32)");
     static_assert(NS <= 16, "slot code fits in 4 bits");
@@ -70,15 +71,15 @@ __device__ __forceinline__ int mod_small(int q) {
 // 2D DFT of the real values v (slot s = pixel (G s + h, c)) into (re, im)
 // (slot s = bin (G s + h, c)).  Active lanes only carry data; inactive lanes
 // compute duplicates that the caller discards.  `ftab` is the DFT table in
-// LDS, `scr` the scratch area (tile: S^2 floats, then the first pass as
-// S^2 float2).
+// LDS, `scr` the scratch area (the tile, S^2 floats, then over it the
+// first pass, S^2 float2).
 template <int S>
 __device__ __forceinline__ void dft2_sg(const float (&v)[SgShape<S>::NS], float (&re)[SgShape<S>::NS],
                                         float (&im)[SgShape<S>::NS], const float2* ftab, float* scr,
                                         int c, int h, bool active) {
     constexpr int G = SgShape<S>::G, NS = SgShape<S>::NS;
-    float* tile = scr;                                      // [m][n]
-    float2* pass1 = reinterpret_cast<float2*>(scr + S * S);  // [k][n]
+    float* tile = scr;                                // [m][n]
+    float2* pass1 = reinterpret_cast<float2*>(scr);   // [k][n], over the tile once it is read
     if (active) {
 #pragma unroll
         for (int s = 0; s < NS; ++s) tile[(G * s + h) * S + c] = v[s];
@@ -100,6 +101,7 @@ __device__ __forceinline__ void dft2_sg(const float (&v)[SgShape<S>::NS], float 
             ai[s] = fmaf(x, f.y, ai[s]);
         }
     }
+    wave_sync();   // every lane has read the tile
     if (active) {
 #pragma unroll
         for (int s = 0; s < NS; ++s) pass1[(G * s + h) * S + c] = make_float2(ar[s], ai[s]);
