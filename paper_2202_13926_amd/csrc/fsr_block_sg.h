@@ -261,8 +261,23 @@ __device__ __forceinline__ void reconstruct_block_sg(const BlockJob& jb, int B, 
             const int slot = 15 - (int)(mx & 15u);
             const int u = G * slot + ln / S, v = ln % S;
             const int idx = u * S + v;
-            const float pr = readlane_f(xr[slot], ln);
-            const float pim = readlane_f(xi[slot], ln);
+            // the winner's slot is uniform: with few slots, branch on it
+            // (scalar) and read two fixed registers instead of selecting
+            // among the slots on the vector ALUs; with many, the compiler's
+            // relative move is cheaper than the branches
+            float pr = 0.0f, pim = 0.0f;
+            if constexpr (NS <= 4) {
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    if (slot == s) {
+                        pr = readlane_f(xr[s], ln);
+                        pim = readlane_f(xi[s], ln);
+                    }
+                }
+            } else {
+                pr = readlane_f(xr[slot], ln);
+                pim = readlane_f(xi[slot], ln);
+            }
             const float cr = gi * pr, ci = gi * pim;    // gamma * p (Eqs. 10-11)
             if (jb.log != nullptr && lane == 0) jb.log[it] = (uint16_t)idx;
 
