@@ -45,6 +45,9 @@ fsr_status plan_batch(const fsr_image_desc* descs, int32_t n, const fsr_params* 
     if (n < 0) return errorf(FSR_ERR_INVALID_ARG, "n_images must be >= 0 (got %d)", n);
     if (n > 0 && !descs) return errorf(FSR_ERR_INVALID_ARG, "descs is NULL");
     const int B = params->block;
+    // blocks per wavefront: each image's range in the index space is padded
+    // to a multiple of it, so that no wavefront spans two images
+    const int64_t unit = batch_unit(params->block + 2 * params->border, B);
     std::vector<int64_t> blocks(n);
     for (int32_t i = 0; i < n; ++i) {
         const fsr_image_desc& d = descs[i];
@@ -76,7 +79,7 @@ fsr_status plan_batch(const fsr_image_desc* descs, int32_t n, const fsr_params* 
         e.width = d.width;
         e.iterations = d.iterations;
         e.nbx = (d.width + B - 1) / B;
-        begin += blocks[order[j]];
+        begin += (blocks[order[j]] + unit - 1) / unit * unit;
         plan->work += (double)blocks[order[j]] * (double)(d.iterations + 8);
         plan->max_iterations = std::max(plan->max_iterations, d.iterations);
     }
@@ -142,6 +145,7 @@ fsr_status prepare(fsr_context* ctx, const fsr_image_desc* descs, int32_t n, con
     prep->launch.block = params->block;
     prep->launch.border = params->border;
     prep->launch.support = S;
+    prep->launch.unit = batch_unit(S, params->block);
     prep->launch.gamma = params->gamma;
     prep->launch.dft = params->dft == FSR_DFT_SPLIT_BF16 ? 1 : 0;
     if (schedule) {

@@ -4,10 +4,13 @@
 // a plain grid: fsr_batched_grid_s32) or run persistently, popping `chunk`
 // consecutive blocks at a time from a global counter until the index space
 // is exhausted (fsr_batched_s32).  Supports 8, 16 and 24 have the same two
-// forms (fsr_batched_grid_sg, fsr_batched_sg).  Each block runs the same
-// arithmetic as in the one-image kernel, so its result does not depend on the
-// batch it is part of.
+// forms (fsr_batched_grid_sg, fsr_batched_sg); at S = 8 with B <= 4 a
+// wavefront takes units of eight blocks of one image (fsr_batched_grid_multi,
+// fsr_batched_multi), every image's block range then being padded to a
+// multiple of eight.  Each block runs the same arithmetic as in the one-image
+// kernel, so its result does not depend on the batch it is part of.
 #include "fsr_block.h"
+#include "fsr_block_multi.h"
 #include "fsr_block_sg.h"
 
 namespace fsr {
@@ -133,6 +136,91 @@ __global__ __launch_bounds__(64 * kWaves) void fsr_batched_sg(BatchLaunch p) {
     queue_body<kWaves, S, kDftFft32>(p, lds);
 }
 
+// ---- S = 8, B <= 4: units of eight blocks of one image
+__device__ __forceinline__ MultiJob batch_multi_job(const BatchLaunch& p, int64_t g, int img) {
+    const DevDesc& d = p.descs[img];
+    MultiJob jb;
+    jb.image = d.image;
+    jb.mask = d.mask;
+    jb.out = d.out;
+    jb.argmax_log = d.argmax_log;
+    jb.height = d.height;
+    jb.width = d.width;
+    jb.stride = d.stride;
+    jb.iterations = d.iterations;
+    jb.nbx = d.nbx;
+    jb.first_block = g - d.block_begin;
+    jb.n_blocks = (int64_t)((d.height + p.block - 1) / p.block) * d.nbx;
+    return jb;
+}
+
+template <int kWaves, int T>
+__global__ __launch_bounds__(64 * kWaves) void fsr_batched_grid_multi(BatchLaunch p) {
+    constexpr int kUnit = MultiShape<8, T>::NB;
+    __shared__ __align__(16) float lds[kWaves * MultiShape<8, T>::kLdsFloats];
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t units = p.total_blocks / kUnit;
+    const int64_t groups = (units + kWaves - 1) / kWaves;
+    const int64_t unit = xcd_contiguous(blockIdx.x, groups) * kWaves + wave;
+    if (unit >= units) return;
+    const int64_t g = unit * kUnit;
+    int img = 0;
+    int64_t img_begin = 0, img_end = 0;
+    locate(p, g, img, img_begin, img_end);
+    reconstruct_multi<8, T>(batch_multi_job(p, g, img), p.block, p.border, p.gamma, p.tab,
+                            lds + wave * MultiShape<8, T>::kLdsFloats);
+}
+
+template <int kWaves, int T>
+__global__ __launch_bounds__(64 * kWaves) void fsr_batched_multi(BatchLaunch p) {
+    constexpr int kUnit = MultiShape<8, T>::NB;
+    __shared__ __align__(16) float lds[kWaves * MultiShape<8, T>::kLdsFloats];
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    float* mine = lds + wave * MultiShape<8, T>::kLdsFloats;
+    const int64_t units = p.total_blocks / kUnit;
+    int64_t next = 0, end = 0;   // units this wavefront still owns
+    int img = 0;
+    int64_t img_begin = 0, img_end = 0;
+    for (;;) {
+        if (next >= end) {
+            unsigned start = 0;
+            if (lane == 0) start = atomicAdd(p.counter, (unsigned)p.chunk);
+            start = __builtin_amdgcn_readfirstlane(start);
+            if ((int64_t)start >= units) break;   // every wavefront ends here
+            next = start;
+            end = next + p.chunk;
+            if (end > units) end = units;
+        }
+        const int64_t g = next * kUnit;
+        locate(p, g, img, img_begin, img_end);
+        reconstruct_multi<8, T, true>(batch_multi_job(p, g, img), p.block, p.border, p.gamma, p.tab, mine);
+        ++next;
+    }
+}
+
+template <int T>
+static hipError_t launch_waves_multi(const BatchLaunch& p, int waves_per_group, dim3 grid, dim3 block,
+                                     hipStream_t stream) {
+    const bool queue = p.chunk > 0;
+    switch (waves_per_group) {
+    case 1:
+        if (queue) hipLaunchKernelGGL((fsr_batched_multi<1, T>), grid, block, 0, stream, p);
+        else hipLaunchKernelGGL((fsr_batched_grid_multi<1, T>), grid, block, 0, stream, p);
+        break;
+    case 2:
+        if (queue) hipLaunchKernelGGL((fsr_batched_multi<2, T>), grid, block, 0, stream, p);
+        else hipLaunchKernelGGL((fsr_batched_grid_multi<2, T>), grid, block, 0, stream, p);
+        break;
+    case 4:
+        if (queue) hipLaunchKernelGGL((fsr_batched_multi<4, T>), grid, block, 0, stream, p);
+        else hipLaunchKernelGGL((fsr_batched_grid_multi<4, T>), grid, block, 0, stream, p);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <int kDft>
 static hipError_t launch_waves(const BatchLaunch& p, int waves_per_group, dim3 grid, dim3 block,
                                hipStream_t stream) {
@@ -184,6 +272,10 @@ static hipError_t resident(K kernel, int waves_per_group, int* groups) {
 
 template <int kWaves>
 static hipError_t resident_of(const BatchLaunch& p, int* groups) {
+    if (p.unit == 8) {
+        if (p.block * p.block <= 8) return resident(fsr_batched_multi<kWaves, 1>, kWaves, groups);
+        return resident(fsr_batched_multi<kWaves, 2>, kWaves, groups);
+    }
     switch (p.support) {
     case 8: return resident(fsr_batched_sg<kWaves, 8>, kWaves, groups);
     case 16: return resident(fsr_batched_sg<kWaves, 16>, kWaves, groups);
@@ -207,12 +299,18 @@ hipError_t batched_resident_groups(const BatchLaunch& p, int waves_per_group, in
 hipError_t launch_batched(const BatchLaunch& p, int waves_per_group, int64_t groups,
                           hipStream_t stream) {
     if (p.total_blocks <= 0) return hipSuccess;
+    if (p.unit != 1 && p.unit != 8) return hipErrorInvalidValue;
     if (p.chunk > 0) {
         hipLaunchKernelGGL(fsr_queue_reset, dim3(1), dim3(64), 0, stream, p.counter);
     } else {
-        groups = (p.total_blocks + waves_per_group - 1) / waves_per_group;
+        const int64_t units = p.total_blocks / p.unit;
+        groups = (units + waves_per_group - 1) / waves_per_group;
     }
     const dim3 grid((unsigned)groups), block(64 * waves_per_group);
+    if (p.unit == 8) {
+        if (p.block * p.block <= 8) return launch_waves_multi<1>(p, waves_per_group, grid, block, stream);
+        return launch_waves_multi<2>(p, waves_per_group, grid, block, stream);
+    }
     switch (p.support) {
     case kS: break;
     case 8: return launch_waves_sg<8>(p, waves_per_group, grid, block, stream);

@@ -164,16 +164,39 @@ __device__ __forceinline__ void residual_at(const float (&xr)[S], const float (&
     ti = blend(m2, i2[1], i2[0]);
 }
 
-template <int S, int T>
-__device__ __forceinline__ void reconstruct_multi(const PlainLaunch& p, int64_t wave, float* lds) {
+// Up to eight consecutive blocks of one image: blocks first_block ..
+// first_block + 7 that lie below n_blocks (the others idle and write
+// nothing).
+struct MultiJob {
+    const float* image;
+    const uint8_t* mask;
+    float* out;
+    uint16_t* argmax_log;   // nullable: n_blocks x iterations for the image
+    int32_t height, width;
+    int64_t stride;
+    int32_t iterations;
+    int32_t nbx;            // blocks per row
+    int64_t first_block;
+    int64_t n_blocks;
+};
+
+// kPersistent: the caller loops over units of eight blocks; as in the other
+// block routines the lane index and table pointers are then made opaque.
+template <int S, int T, bool kPersistent = false>
+__device__ __forceinline__ void reconstruct_multi(const MultiJob& im, int B, int L, float gamma,
+                                                  const BlockTables& tab_in, float* lds) {
     using Sh = MultiShape<S, T>;
     constexpr int NB = Sh::NB, G1 = Sh::G1, NS1 = Sh::NS1;
-    const int lane = (int)(threadIdx.x & 63);
+    const int lane = kPersistent ? opaque((int)(threadIdx.x & 63)) : (int)(threadIdx.x & 63);
+    BlockTables tab = tab_in;
+    if constexpr (kPersistent) {
+        tab.rho_pow = opaque_ptr(tab_in.rho_pow);
+        tab.freq_w = opaque_ptr(tab_in.freq_w);
+        tab.dft_sg = opaque_ptr(tab_in.dft_sg);
+    }
     const int b = lane / S, c = lane % S, first = b * S;
-    const ImageDesc& im = p.img;
-    const int B = p.block, L = p.border;
-    const int64_t blk = wave * NB + b;
-    const bool valid = blk < p.n_blocks;
+    const int64_t blk = im.first_block + b;
+    const bool valid = blk < im.n_blocks;
     const int32_t blk32 = valid ? (int32_t)blk : 0;   // block counts are below 2^31
     const int by = blk32 / im.nbx, bx = blk32 - by * im.nbx;
     const int y0 = by * B - L, x0 = bx * B - L;
@@ -187,7 +210,7 @@ __device__ __forceinline__ void reconstruct_multi(const PlainLaunch& p, int64_t 
 
     // ---- DFT table into LDS (the same for every block)
     {
-        const global_t<const uint64_t>* src = global_ptr(reinterpret_cast<const uint64_t*>(p.tab.dft_sg));
+        const global_t<const uint64_t>* src = global_ptr(reinterpret_cast<const uint64_t*>(tab.dft_sg));
         uint64_t* dst = reinterpret_cast<uint64_t*>(ftab);
         for (int i = lane; i < S * S; i += 64) dst[i] = src[i];
     }
@@ -204,7 +227,7 @@ __device__ __forceinline__ void reconstruct_multi(const PlainLaunch& p, int64_t 
         const int64_t off = in ? (int64_t)y * im.stride + x : 0;
         const uint8_t kraw = mask[off];
         const float fraw = image[off];
-        const float rp = global_ptr(p.tab.rho_pow)[s * S + c];
+        const float rp = global_ptr(tab.rho_pow)[s * S + c];
         const uint8_t k = in ? kraw : (uint8_t)0;
         known_here |= k;
         xr[s] = k ? fraw : 0.0f;
@@ -264,10 +287,10 @@ __device__ __forceinline__ void reconstruct_multi(const PlainLaunch& p, int64_t 
     }
     // W[0][0] of this block lives on its first lane, slot 0
     const float w00 = __int_as_float(__builtin_amdgcn_ds_bpermute(4 * first, __float_as_int(wr[0])));
-    const float gi = w00 > 0.0f ? p.gamma / w00 : 0.0f;
+    const float gi = w00 > 0.0f ? gamma / w00 : 0.0f;
     float wf[S];
 #pragma unroll
-    for (int s = 0; s < S; ++s) wf[s] = global_ptr(p.tab.freq_w)[s * S + c];
+    for (int s = 0; s < S; ++s) wf[s] = global_ptr(tab.freq_w)[s * S + c];
     // lane c of each block holds F[1][c] = exp(-j 2 pi c / S), read before W
     // overwrites the table
     const float2 tw = ftab[S + c];

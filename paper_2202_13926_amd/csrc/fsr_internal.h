@@ -79,7 +79,15 @@ struct BatchLaunch {
     float gamma;
     BlockTables tab;
     int32_t dft;            // 0: FP32 FFTs, 1: split-bf16 matrix products
+    int32_t unit;           // blocks per wavefront: 1, or 8 (S = 8, B <= 4);
+                            // every image's block range is a multiple of it,
+                            // and chunk counts units
 };
+
+// Blocks per wavefront of the batched kernels for these parameters.
+inline int32_t batch_unit(int32_t support, int32_t block) {
+    return support == 8 && block * block <= 16 ? 8 : 1;
+}
 
 // Launches the queue reset (when chunk > 0) and the batched kernel with
 // `waves_per_group` wavefronts per workgroup and `groups` workgroups

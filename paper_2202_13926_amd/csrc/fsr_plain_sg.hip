@@ -18,8 +18,22 @@ __global__ __launch_bounds__(64) void fsr_plain_sg(PlainLaunch p) {
 template <int S, int T>
 __global__ __launch_bounds__(64) void fsr_plain_multi(PlainLaunch p) {
     __shared__ __align__(16) float lds[MultiShape<S, T>::kLdsFloats];
-    const int64_t waves = (p.n_blocks + MultiShape<S, T>::NB - 1) / MultiShape<S, T>::NB;
-    reconstruct_multi<S, T>(p, xcd_contiguous(blockIdx.x, waves), lds);
+    constexpr int NB = MultiShape<S, T>::NB;
+    const int64_t waves = (p.n_blocks + NB - 1) / NB;
+    const ImageDesc& im = p.img;
+    MultiJob jb;
+    jb.image = im.image;
+    jb.mask = im.mask;
+    jb.out = im.out;
+    jb.argmax_log = im.argmax_log;
+    jb.height = im.height;
+    jb.width = im.width;
+    jb.stride = im.stride;
+    jb.iterations = im.iterations;
+    jb.nbx = im.nbx;
+    jb.first_block = xcd_contiguous(blockIdx.x, waves) * NB;
+    jb.n_blocks = p.n_blocks;
+    reconstruct_multi<S, T>(jb, p.block, p.border, p.gamma, p.tab, lds);
 }
 
 template <int S, int T>
