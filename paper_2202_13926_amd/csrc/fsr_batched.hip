@@ -9,6 +9,7 @@
 // fsr_batched_multi), every image's block range then being padded to a
 // multiple of eight.  Each block runs the same arithmetic as in the one-image
 // kernel, so its result does not depend on the batch it is part of.
+#include "fsr_batch_internal.h"
 #include "fsr_block.h"
 #include "fsr_block_multi.h"
 #include "fsr_block_sg.h"

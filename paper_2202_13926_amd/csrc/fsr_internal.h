@@ -53,51 +53,4 @@ struct PlainLaunch {
 hipError_t launch_plain(const PlainLaunch& p, hipStream_t stream);
 hipError_t launch_plain_sg(const PlainLaunch& p, hipStream_t stream);   // S = 8, 16, 24
 
-// Device-side descriptor of one image of a batch (64 bytes).  Images are
-// stored in queue order; block_begin is the prefix sum of block counts.
-struct DevDesc {
-    const float* image;
-    const uint8_t* mask;
-    float* out;
-    uint16_t* argmax_log;
-    int64_t stride;
-    int64_t block_begin;
-    int32_t height, width;
-    int32_t iterations;
-    int32_t nbx;
-};
-static_assert(sizeof(DevDesc) == 64, "descriptor layout");
-
-struct BatchLaunch {
-    const DevDesc* descs;   // device, n_images entries
-    unsigned* counter;      // device queue head (reset before every launch)
-    int64_t total_blocks;
-    int32_t n_images;
-    int32_t chunk;          // blocks per queue pop; 0 = one wavefront per block, no queue
-    int32_t block, border;
-    int32_t support;        // S = B + 2L: 32, or 8, 16, 24 (FP32 DFTs only)
-    float gamma;
-    BlockTables tab;
-    int32_t dft;            // 0: FP32 FFTs, 1: split-bf16 matrix products
-    int32_t unit;           // blocks per wavefront: 1, or 8 (S = 8, B <= 4);
-                            // every image's block range is a multiple of it,
-                            // and chunk counts units
-};
-
-// Blocks per wavefront of the batched kernels for these parameters.
-inline int32_t batch_unit(int32_t support, int32_t block) {
-    return support == 8 && block * block <= 16 ? 8 : 1;
-}
-
-// Launches the queue reset (when chunk > 0) and the batched kernel with
-// `waves_per_group` wavefronts per workgroup and `groups` workgroups
-// (persistent mode) on `stream`.
-hipError_t launch_batched(const BatchLaunch& p, int waves_per_group, int64_t groups,
-                          hipStream_t stream);
-
-// Workgroups of `waves_per_group` wavefronts that one compute unit holds at
-// once in the persistent batched kernel for p.support and p.dft (register
-// and LDS limits, from the HIP occupancy calculator).
-hipError_t batched_resident_groups(const BatchLaunch& p, int waves_per_group, int* groups);
-
 }  // namespace fsr

@@ -8,6 +8,7 @@
 #include <mutex>
 
 #include "fsr.h"
+#include "fsr_batch_internal.h"
 #include "fsr_internal.h"
 
 namespace fsr {
