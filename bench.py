@@ -485,11 +485,15 @@ def bench_realtime_s16(ctx, seconds: float = 5.0, fps: float = 60.0, budget: int
         span = a[:, 3].max() - a[:, 0].min()
         per = {}
         for h, label in names.items():
-            m = lat[a[:, 5] == h]
+            sel = a[:, 5] == h
+            m = lat[sel]
             per[label] = {"p50_ms": round(float(np.percentile(m, 50)), 3),
                           "p99_ms": round(float(np.percentile(m, 99)), 3),
                           "max_ms": round(float(m.max()), 3),
-                          "missed_deadline": int((m > deadline_ms).sum()), "frames": int(m.size)}
+                          "missed_deadline": int((m > deadline_ms).sum()), "frames": int(m.size),
+                          # where the time goes: submit -> launch, launch -> done (medians)
+                          "to_launch_ms": round(float(np.median(a[sel, 2] - a[sel, 0]) * 1e3), 3),
+                          "launch_to_done_ms": round(float(np.median(a[sel, 3] - a[sel, 2]) * 1e3), 3)}
         out[name] = {"by_resolution": per,
                      "throughput_mpx_s": round(float(a[:, 4].sum() / span / 1e6), 2),
                      "frames_per_launch": round(st["completed"] / max(st["launches"], 1), 3),

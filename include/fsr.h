@@ -284,7 +284,12 @@ typedef struct fsr_server fsr_server;
  * the in-flight limit allow; an admitted request is copied into the arena
  * and reconstructed there, and its output stays in device memory until
  * fetched or released.  Each result is bitwise identical to fsr_reconstruct
- * on the same frame, whatever else shares its launch.
+ * on the same frame, whatever else shares its launch.  While a batch runs, a
+ * second one starts beside it on the other compute stream only if it is at
+ * most a quarter of the running batch's work.  The compute streams are
+ * created with a CU mask enabling every compute unit (each then has a
+ * hardware queue of its own) and therefore synchronise with the legacy null
+ * stream.
  */
 FSR_API fsr_status fsr_server_create(fsr_context *ctx, const fsr_params *params,
                                      const fsr_server_config *cfg, fsr_server **out);

@@ -48,6 +48,23 @@ inline int32_t batch_unit(int32_t support, int32_t block) {
 hipError_t launch_batched(const BatchLaunch& p, int waves_per_group, int64_t groups,
                           hipStream_t stream);
 
+// Device copies written by kernels rather than by the runtime's copy
+// commands: on this runtime a copy enqueued on one stream does not start
+// while a kernel of another stream runs, whereas kernels of different
+// streams share the device.  Keeping the launch path of a batch free of
+// copies lets a small batch run beside a large one.
+constexpr int kDescsPerKernel = 16;    // descriptors carried by one kernel's arguments
+constexpr int kDescKernelMax = 64;     // larger tables go through a pinned copy
+
+// Writes the n <= kDescKernelMax descriptors of `table` to `dst` (device)
+// with kernels on `stream`.
+hipError_t launch_write_descs(const DevDesc* table, int n, DevDesc* dst, hipStream_t stream);
+
+// Copies a height x width_bytes region between pitched buffers that the
+// device can address (device memory, or pinned host memory) with a kernel.
+hipError_t launch_copy2d(void* dst, size_t dst_pitch, const void* src, size_t src_pitch, size_t width_bytes,
+                         size_t height, hipStream_t stream);
+
 // Workgroups of `waves_per_group` wavefronts that one compute unit holds at
 // once in the persistent batched kernel for p.support and p.dft (register
 // and LDS limits, from the HIP occupancy calculator).

@@ -165,14 +165,22 @@ fsr_status prepare(fsr_context* ctx, const fsr_image_desc* descs, int32_t n, con
     return FSR_OK;
 }
 
-// Copies the descriptor table into the workspace, ordered on `stream`,
-// through a pinned staging slot (the previous copy out of it must be done
-// before it is overwritten).
+// Puts the descriptor table into the workspace, ordered on `stream`: up to
+// kDescKernelMax descriptors with kernels, more through a pinned staging slot
+// (the previous copy out of it must be done before it is overwritten).
 fsr_status upload_async(const BatchPlan& plan, void* workspace, hipStream_t stream,
                         StagingSlot* slot) {
     const size_t bytes = plan.table.size() * sizeof(DevDesc);
     if (bytes == 0) return FSR_OK;
     hipError_t e;
+    if (plan.table.size() <= (size_t)kDescKernelMax) {
+        // small tables travel as kernel arguments: no copy command, so the
+        // launch can run beside kernels of other streams
+        e = launch_write_descs(plan.table.data(), (int)plan.table.size(),
+                               reinterpret_cast<DevDesc*>(static_cast<char*>(workspace) + kCtrlBytes), stream);
+        if (e != hipSuccess) return hip_fail(e, "descriptor upload");
+        return FSR_OK;
+    }
     if (slot->done) {
         if ((e = hipEventSynchronize(slot->done)) != hipSuccess) return hip_fail(e, "hipEventSynchronize");
     } else if ((e = hipEventCreateWithFlags(&slot->done, hipEventDisableTiming)) != hipSuccess) {

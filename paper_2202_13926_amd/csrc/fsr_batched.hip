@@ -20,6 +20,66 @@ __global__ void fsr_queue_reset(unsigned* counter) {
     if (threadIdx.x == 0) *counter = 0u;
 }
 
+struct DescChunk {
+    DevDesc d[kDescsPerKernel];
+};
+
+// Thread t < n writes descriptor t (64 bytes as four 16-byte stores).
+__global__ __launch_bounds__(64) void fsr_write_descs(DescChunk c, DevDesc* dst, int n) {
+    const int t = threadIdx.x;
+    if (t >= n) return;
+    const uint4* s = reinterpret_cast<const uint4*>(&c.d[t]);
+    uint4* o = reinterpret_cast<uint4*>(dst + t);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) o[i] = s[i];
+}
+
+hipError_t launch_write_descs(const DevDesc* table, int n, DevDesc* dst, hipStream_t stream) {
+    if (n < 0 || n > kDescKernelMax) return hipErrorInvalidValue;
+    for (int first = 0; first < n; first += kDescsPerKernel) {
+        const int m = n - first < kDescsPerKernel ? n - first : kDescsPerKernel;
+        DescChunk c{};
+        for (int i = 0; i < m; ++i) c.d[i] = table[first + i];
+        hipLaunchKernelGGL(fsr_write_descs, dim3(1), dim3(64), 0, stream, c, dst + first, m);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Row y of the region in blockIdx.y-strided passes; 16-byte words where the
+// region's width, pitches and addresses allow, else bytes.  Workgroups of
+// one wavefront: while another kernel keeps every compute unit busy, a
+// workgroup of several wavefronts waits for that many free slots on one
+// compute unit, in practice for the other kernel to drain.
+template <typename W>
+__global__ __launch_bounds__(64) void fsr_copy2d(char* dst, size_t dst_pitch, const char* src, size_t src_pitch,
+                                                  size_t words, size_t height) {
+    for (size_t y = blockIdx.y; y < height; y += gridDim.y) {
+        W* d = reinterpret_cast<W*>(dst + y * dst_pitch);
+        const W* s = reinterpret_cast<const W*>(src + y * src_pitch);
+        for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < words; i += (size_t)gridDim.x * blockDim.x)
+            d[i] = s[i];
+    }
+}
+
+hipError_t launch_copy2d(void* dst, size_t dst_pitch, const void* src, size_t src_pitch, size_t width_bytes,
+                         size_t height, hipStream_t stream) {
+    if (width_bytes == 0 || height == 0) return hipSuccess;
+    const bool wide = (width_bytes % 16 == 0) && (dst_pitch % 16 == 0) && (src_pitch % 16 == 0) &&
+                      ((uintptr_t)dst % 16 == 0) && ((uintptr_t)src % 16 == 0);
+    const size_t words = wide ? width_bytes / 16 : width_bytes;
+    const unsigned gx = (unsigned)((words + 63) / 64 < 64 ? (words + 63) / 64 : 64);
+    const unsigned gy = (unsigned)(height < 4096 ? height : 4096);
+    if (wide)
+        hipLaunchKernelGGL(fsr_copy2d<uint4>, dim3(gx, gy), dim3(64), 0, stream, static_cast<char*>(dst),
+                           dst_pitch, static_cast<const char*>(src), src_pitch, words, height);
+    else
+        hipLaunchKernelGGL(fsr_copy2d<uint8_t>, dim3(gx, gy), dim3(64), 0, stream, static_cast<char*>(dst),
+                           dst_pitch, static_cast<const char*>(src), src_pitch, words, height);
+    return hipGetLastError();
+}
+
 // Image of global block g: the cached one when g still lies in [begin, end),
 // else a binary search over the descriptors (sorted by block_begin).
 __device__ __forceinline__ void locate(const BatchLaunch& p, int64_t g, int& img, int64_t& begin,
