@@ -162,3 +162,36 @@ def test_not_ready_and_shutdown_with_pending_work(ctx):
         t = srv2.submit(ti, tm, 10)
         srv2.wait(t, 20000)
         srv2.release(t)
+
+
+def test_every_upload_route_gives_the_same_result(ctx):
+    """Inputs reach the server's arena by a copy kernel (device memory, strided
+    or not, and pinned host frames up to 4 MiB) or by the runtime's copy
+    (larger pinned host frames, pageable host memory); every route must give
+    the one-image result."""
+    announce("uploads: device strided, pinned small and large, pageable")
+    small = frames(6)[3]                                   # 128 x 96, pinned: copy kernel
+    h, w = 1000, 1100                                      # 5.5 MB: the runtime's copy when pinned
+    large = (synth.make_image(h, w, 611).astype(np.float32), synth.make_mask("uniform:0.3", h, w, 612), 40)
+    refs = [alone(ctx, *small), alone(ctx, *large)]
+    cfg = fsr.make_server_config(hbm_budget=256 << 20, max_inflight=16, max_batch=4, streams=2)
+    with fsr.Server(ctx, fsr.make_params(), cfg) as srv:
+        tickets = []
+        for (img, mask, it), ref in zip((small, large), refs):
+            H, W = img.shape
+            pad = 7
+            bi = torch.zeros((H, W + pad), dtype=torch.float32, device=DEV)
+            bm = torch.zeros((H, W + pad), dtype=torch.uint8, device=DEV)
+            bi[:, :W] = torch.from_numpy(img)
+            bm[:, :W] = torch.from_numpy(mask)
+            torch.cuda.synchronize()
+            routes = [("device strided", bi[:, :W], bm[:, :W]),
+                      ("pinned", torch.from_numpy(img).pin_memory(), torch.from_numpy(mask).pin_memory()),
+                      ("pageable", torch.from_numpy(img.copy()), torch.from_numpy(mask.copy()))]
+            for name, ti, tm in routes:
+                tickets.append((name, H, W, ref, srv.submit(ti, tm, it)))
+        for name, H, W, ref, t in tickets:
+            srv.wait(t, 30000)
+            host = torch.empty((H, W), dtype=torch.float32)
+            srv.result(t, host)
+            assert np.array_equal(host.numpy(), ref), f"{name} {H}x{W}"
