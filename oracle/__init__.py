@@ -1,4 +1,5 @@
-"""FP64 CPU oracle for block-independent FSR (test infrastructure).
+"""FP64 CPU oracle for FSR (test infrastructure): the block-independent
+method and the sequential variant that reuses reconstructed pixels.
 
 Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  It wraps ``fsr_oracle.c`` (plain C,
@@ -59,6 +60,13 @@ def _load():
                                                 c_int, c_double, c_double, c_int, c_int, i64p, c_long,
                                                 dp, u16p, dp, c_int]
         lib.fsro_reconstruct_blocks.restype = c_long
+        lib.fsro_block_weighted.argtypes = [c_int, c_int, c_double, c_int, c_int, dp, dp,
+                                            dp, dp, dp, dp, u16p, dp]
+        lib.fsro_block_weighted.restype = c_int
+        lib.fsro_reconstruct_reuse.argtypes = [dp, u8p, dp, c_int, c_int, c_long, c_int, c_int,
+                                               c_int, c_double, c_double, c_double, c_int, c_int,
+                                               u16p]
+        lib.fsro_reconstruct_reuse.restype = c_long
         lib.fsro_max_threads.restype = c_int
         _lib = lib
     return _lib
@@ -142,6 +150,25 @@ def block(ft: np.ndarray, known: np.ndarray, iters: int, rho: float, gamma: floa
             "empty": bool(empty)}
 
 
+def block_weighted(ft: np.ndarray, w: np.ndarray, iters: int, gamma: float,
+                   tie_larger: bool = False, decision: int = DECISION_FP64):
+    """Run O3-O6 on one support block with a given spatial weight ``w``
+    (S x S).  Returns the same dict as :func:`block`."""
+    ft = _f64(ft)
+    w = _f64(w)
+    S = ft.shape[0]
+    Gr, Gi, Rr, Ri = (np.empty((S, S)) for _ in range(4))
+    idx = np.empty(max(iters, 1), np.uint16)
+    p = np.empty(2 * max(iters, 1))
+    D = ctypes.c_double
+    empty = _load().fsro_block_weighted(S, iters, gamma, int(tie_larger), int(decision),
+                                        _p(ft, D), _p(w, D), _p(Gr, D), _p(Gi, D), _p(Rr, D),
+                                        _p(Ri, D), _p(idx, ctypes.c_uint16), _p(p, D))
+    return {"G": Gr + 1j * Gi, "R": Rr + 1j * Ri, "Gr": Gr, "Gi": Gi, "Rr": Rr, "Ri": Ri,
+            "idx": idx[:iters].copy(), "p": (p[0::2] + 1j * p[1::2])[:iters],
+            "empty": bool(empty)}
+
+
 def model_pixel(G: np.ndarray, m: int, n: int) -> float:
     S = G.shape[0]
     Gr, Gi = _f64(G.real), _f64(G.imag)
@@ -193,6 +220,30 @@ def reconstruct_blocks(image: np.ndarray, mask: np.ndarray, block_ids, iters: in
         lg = lg[:, :iters]
     p = None if lp is None else (lp[:, :iters, 0] + 1j * lp[:, :iters, 1])
     return tg, lg, p, int(n_empty)
+
+
+def reconstruct_reuse(image: np.ndarray, mask: np.ndarray, iters: int, delta: float = 0.5,
+                      block_size: int = 4, border: int = 14, rho: float = 0.7,
+                      gamma: float = 0.5, tie_larger: bool = False, log: bool = False,
+                      decision: int = DECISION_FP64):
+    """Sequential FP64 reconstruction that reuses reconstructed pixels (O9):
+    blocks in raster order, missing pixels of earlier blocks' targets taking
+    part with their reconstruction and the weight ``delta`` rho^dist.
+    Returns ``(out, log_idx, n_empty)`` like :func:`reconstruct`."""
+    img = _f64(image)
+    m = _u8(mask)
+    H, W = img.shape
+    B = block_size
+    N = (-(-H // B)) * (-(-W // B))
+    out = np.zeros_like(img)
+    lg = np.empty((N, max(iters, 1)), np.uint16) if log else None
+    n_empty = _load().fsro_reconstruct_reuse(_p(img, ctypes.c_double), _p(m, ctypes.c_uint8),
+                                             _p(out, ctypes.c_double), H, W, W, B, border, iters,
+                                             rho, gamma, delta, int(tie_larger), int(decision),
+                                             _p(lg, ctypes.c_uint16))
+    if lg is not None:
+        lg = lg[:, :iters]
+    return out, lg, int(n_empty)
 
 
 def max_threads() -> int:

@@ -21,6 +21,11 @@
  *       cyclic indices as in Eqs. 14-15)
  *   O7  g = inverse DFT2 of G (1/S^2, e^{+j}) on the target pixels
  *   O8  output = f~ on known pixels, Re g on unknown ones         (Sec. II)
+ *   O9  the sequential variant that reuses reconstructed pixels, the
+ *       original FSR that the paper departs from (Sec. II): blocks in
+ *       raster order, and a missing support pixel in the target of an
+ *       earlier block counts as known with its reconstructed value and the
+ *       weight delta rho^dist (fsro_reconstruct_reuse)
  *
  * Readings of points the paper leaves open (each is listed with its reason
  * in the design notes):
@@ -39,6 +44,10 @@
  *   - A support with no known pixel (W[0,0] == 0) runs no iteration; its
  *     unknown target pixels are 0 and its log entries are 0xFFFF.
  *   - Unknown pixels take Re g; outputs are not clipped.
+ *   - O9: "earlier" is raster order of the blocks (block row, then block
+ *     column); delta is a parameter in [0, 1] (the original method's
+ *     publications use 0.5); delta = 0 reuses nothing, so the variant then
+ *     equals the block-independent method.
  *
  * Build: gcc -O2 -std=c11 -fPIC -shared -fopenmp -ffp-contract=off
  * (no fast-math: the symmetry arguments above rely on IEEE rounding).
@@ -166,19 +175,42 @@ FSRO_API void fsro_dft2_real(int S, const double *x, double *Xr, double *Xi)
  *   log_p   2I entries: projection coefficient p (re, im) per iteration
  * Returns 1 when the support holds no known pixel (no iteration ran), else 0.
  */
+FSRO_API int fsro_block_weighted(int S, int iters, double gamma, int tie_larger, int decision,
+                                 const double *ft, const double *w,
+                                 double *Gr_out, double *Gi_out, double *Rr_out, double *Ri_out,
+                                 uint16_t *log_idx, double *log_p);
+
 FSRO_API int fsro_block(int S, int iters, double rho, double gamma, int tie_larger,
                         int decision, const double *ft, const uint8_t *known,
                         double *Gr_out, double *Gi_out, double *Rr_out, double *Ri_out,
                         uint16_t *log_idx, double *log_p)
 {
+    double *w = malloc(sizeof(double) * S * S);
+    fsro_spatial_weight(S, rho, known, w);                /* O2 */
+    int empty = fsro_block_weighted(S, iters, gamma, tie_larger, decision, ft, w, Gr_out, Gi_out,
+                                    Rr_out, Ri_out, log_idx, log_p);
+    free(w);
+    return empty;
+}
+
+/*
+ * Steps O3-O6 for a support whose spatial weight w (S x S, zero on pixels
+ * that do not take part) is given; fsro_block passes the weight of Eq. 5,
+ * the reuse variant (O9) one with a third class of pixels.  Outputs as for
+ * fsro_block; returns 1 when W[0,0] is not positive (no iteration ran).
+ */
+FSRO_API int fsro_block_weighted(int S, int iters, double gamma, int tie_larger, int decision,
+                                 const double *ft, const double *w,
+                                 double *Gr_out, double *Gi_out, double *Rr_out, double *Ri_out,
+                                 uint16_t *log_idx, double *log_p)
+{
     const int n2 = S * S;
-    double *w = malloc(sizeof(double) * n2), *x = malloc(sizeof(double) * n2);
+    double *x = malloc(sizeof(double) * n2);
     double *wf = malloc(sizeof(double) * n2);
     double *Rr = malloc(sizeof(double) * n2), *Ri = malloc(sizeof(double) * n2);
     double *Wr = malloc(sizeof(double) * n2), *Wi = malloc(sizeof(double) * n2);
     double *Gr = calloc(n2, sizeof(double)), *Gi = calloc(n2, sizeof(double));
 
-    fsro_spatial_weight(S, rho, known, w);                /* O2 */
     fsro_freq_weight(S, wf);                              /* O3 */
     for (int i = 0; i < n2; ++i) x[i] = ft[i] * w[i];
     fsro_dft2_real(S, x, Rr, Ri);                         /* O4 */
@@ -223,7 +255,7 @@ FSRO_API int fsro_block(int S, int iters, double rho, double gamma, int tie_larg
     if (Gi_out) memcpy(Gi_out, Gi, sizeof(double) * n2);
     if (Rr_out) memcpy(Rr_out, Rr, sizeof(double) * n2);
     if (Ri_out) memcpy(Ri_out, Ri, sizeof(double) * n2);
-    free(w); free(x); free(wf); free(Rr); free(Ri); free(Wr); free(Wi); free(Gr); free(Gi);
+    free(x); free(wf); free(Rr); free(Ri); free(Wr); free(Wi); free(Gr); free(Gi);
     return empty;
 }
 
@@ -351,6 +383,65 @@ FSRO_API long fsro_reconstruct_blocks(const double *img, const uint8_t *mask,
                                  log_idx ? log_idx + i * (long)iters : NULL,
                                  log_p ? log_p + 2 * i * (long)iters : NULL);
     }
+    return empty;
+}
+
+/*
+ * O9: the sequential variant.  Blocks run one after another in raster order
+ * (block row, then block column).  In the support of block (by, bx) a pixel
+ * takes part
+ *   - as known, weight rho^dist, value from img, where mask marks it;
+ *   - as reused, weight delta rho^dist, value from out, where it is missing
+ *     but lies in the target of an earlier block, which has already written
+ *     its reconstruction to out (only when delta > 0);
+ *   - not at all otherwise (missing pixels of this or later blocks, pixels
+ *     outside the image).
+ * Each block then runs O3-O8 as in the block-independent method and writes
+ * its target to out.  Arguments as for fsro_reconstruct plus delta; out is
+ * read as well as written and must not alias img.  Returns the number of
+ * blocks whose support held no pixel with positive weight.
+ */
+FSRO_API long fsro_reconstruct_reuse(const double *img, const uint8_t *mask, double *out,
+                                     int H, int W, long stride, int B, int L, int iters,
+                                     double rho, double gamma, double delta, int tie_larger,
+                                     int decision, uint16_t *log_idx)
+{
+    const int S = B + 2 * L, n2 = S * S;
+    const int nby = (H + B - 1) / B, nbx = (W + B - 1) / B;
+    double *ft = malloc(sizeof(double) * n2), *w = malloc(sizeof(double) * n2);
+    double *rp = malloc(sizeof(double) * n2);
+    double *Gr = malloc(sizeof(double) * n2), *Gi = malloc(sizeof(double) * n2);
+    uint8_t *all = malloc(n2), *known = malloc(n2);
+    memset(all, 1, n2);
+    fsro_spatial_weight(S, rho, all, rp);                 /* rho^dist everywhere */
+    long empty = 0;
+    for (int by = 0; by < nby; ++by)
+        for (int bx = 0; bx < nbx; ++bx) {
+            const long b = (long)by * nbx + bx;
+            const int y0 = by * B - L, x0 = bx * B - L;
+            for (int m = 0; m < S; ++m)
+                for (int n = 0; n < S; ++n) {
+                    const int y = y0 + m, x = x0 + n, i = m * S + n;
+                    const int in = (y >= 0 && y < H && x >= 0 && x < W);
+                    const int k = in && mask[(long)y * stride + x] != 0;
+                    const int earlier = y < by * B || (y < (by + 1) * B && x < bx * B);
+                    const int reused = in && !k && earlier && delta > 0.0;
+                    known[i] = (uint8_t)k;
+                    ft[i] = k ? img[(long)y * stride + x] : reused ? out[(long)y * stride + x] : 0.0;
+                    w[i] = k ? rp[i] : reused ? delta * rp[i] : 0.0;
+                }
+            empty += fsro_block_weighted(S, iters, gamma, tie_larger, decision, ft, w, Gr, Gi,
+                                         NULL, NULL, log_idx ? log_idx + b * (long)iters : NULL,
+                                         NULL);
+            for (int i = 0; i < B; ++i)                   /* O8 on the target */
+                for (int j = 0; j < B; ++j) {
+                    const int y = by * B + i, x = bx * B + j, m = L + i, n = L + j;
+                    if (y >= H || x >= W) continue;
+                    out[(long)y * stride + x] = known[m * S + n]
+                        ? ft[m * S + n] : fsro_model_pixel(S, Gr, Gi, m, n);
+                }
+        }
+    free(ft); free(w); free(rp); free(Gr); free(Gi); free(all); free(known);
     return empty;
 }
 

@@ -1,0 +1,201 @@
+"""Pins of the oracle's sequential variant that reuses reconstructed pixels.
+
+The paper's method treats every block independently (Sec. II) and says that
+it departs from the original FSR there, which lets pixels reconstructed by
+earlier blocks take part in later supports with a reduced weight.  The
+oracle's `reconstruct_reuse` is that original scheme under the readings in
+its header: blocks in raster order, reused pixels weighted delta rho^dist.
+
+The pins check it against facts that do not depend on its own code:
+delta = 0 is the block-independent method, the first block has nothing to
+reuse, a uniform scaling of the weights changes nothing (Eqs. 7, 10 and 8 are
+homogeneous in w), a brute-force restatement of the raster definition built
+from block ownership, and causality (a change reaches earlier blocks only
+through their own supports; with reuse, also the blocks after the first one
+that sees it).  Planted slips
+in a copy of the C source must fail at least one of them.
+"""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import synth
+
+
+def tiny_case(seed=5, H=22, W=18):
+    img = synth.make_image(H, W, seed)
+    mask = synth.quarter_mask(H, W, seed + 1)
+    return img, mask
+
+
+def bruteforce_reuse(o, img, mask, iters, delta, B, L, rho, gamma):
+    """The raster definition written out pixel by pixel: a support pixel is
+    reused when it is missing and the block that owns it has a smaller raster
+    index than the current one."""
+    H, W = img.shape
+    S = B + 2 * L
+    nby, nbx = -(-H // B), -(-W // B)
+    owner = (np.arange(H)[:, None] // B) * nbx + (np.arange(W)[None, :] // B)
+    rp = o.spatial_weight(np.ones((S, S), np.uint8), rho)
+    out = np.full((H, W), np.nan)
+    logs = []
+    for b in range(nby * nbx):
+        by, bx = divmod(b, nbx)
+        ft, w = np.zeros((S, S)), np.zeros((S, S))
+        for m in range(S):
+            for n in range(S):
+                y, x = by * B - L + m, bx * B - L + n
+                if not (0 <= y < H and 0 <= x < W):
+                    continue
+                if mask[y, x]:
+                    ft[m, n], w[m, n] = img[y, x], rp[m, n]
+                elif owner[y, x] < b and delta > 0:
+                    ft[m, n], w[m, n] = out[y, x], delta * rp[m, n]
+        r = o.block_weighted(ft, w, iters, gamma)
+        logs.append(r["idx"])
+        for i in range(B):
+            for j in range(B):
+                y, x = by * B + i, bx * B + j
+                if y < H and x < W:
+                    out[y, x] = img[y, x] if mask[y, x] else o.model_pixel(r["G"], L + i, L + j)
+    return out, np.array(logs)
+
+
+# ---------------------------------------------------------------- delta = 0
+def test_delta_zero_is_the_block_independent_method(oracle_lib):
+    img, mask = synth.workload("small64").inputs()
+    a, la, ea = oracle_lib.reconstruct(img, mask, 40, log=True)
+    b, lb, eb = oracle_lib.reconstruct_reuse(img, mask, 40, delta=0.0, log=True)
+    assert np.array_equal(a, b) and np.array_equal(la, lb) and ea == eb
+
+
+# ---------------------------------------------------------------- first block
+@pytest.mark.parametrize("delta", [0.25, 0.5, 1.0])
+def test_first_block_has_nothing_to_reuse(oracle_lib, delta):
+    img, mask = synth.workload("small64").inputs()
+    a, la, _ = oracle_lib.reconstruct(img, mask, 40, log=True)
+    b, lb, _ = oracle_lib.reconstruct_reuse(img, mask, 40, delta=delta, log=True)
+    assert np.array_equal(a[:4, :4], b[:4, :4]) and np.array_equal(la[0], lb[0])
+    # and reuse does change later blocks
+    assert not np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------- homogeneity in w
+def test_uniform_weight_scaling_is_invisible(oracle_lib):
+    """Eqs. 7 and 10 are homogeneous in w: R_w and W scale alike, p and the
+    argmax of w_f |R_w|^2 do not change.  Scaling by a power of two is exact
+    in binary floating point, so the result is bitwise the same."""
+    S = 32
+    rng = np.random.default_rng(9)
+    known = (rng.random((S, S)) < 0.3).astype(np.uint8)
+    ft = np.where(known != 0, rng.uniform(0, 255, (S, S)), 0.0)
+    w = oracle_lib.spatial_weight(known, 0.7)
+    base = oracle_lib.block_weighted(ft, w, 50, 0.5)
+    ref = oracle_lib.block(ft, known, 50, 0.7, 0.5)
+    assert np.array_equal(base["G"], ref["G"]) and np.array_equal(base["idx"], ref["idx"])
+    half = oracle_lib.block_weighted(ft, 0.5 * w, 50, 0.5)
+    assert np.array_equal(half["G"], base["G"]) and np.array_equal(half["idx"], base["idx"])
+    odd = oracle_lib.block_weighted(ft, 0.3 * w, 50, 0.5)
+    assert np.array_equal(odd["idx"], base["idx"])
+    assert np.max(np.abs(odd["G"] - base["G"])) <= 1e-9 * np.max(np.abs(base["G"]))
+
+
+# ---------------------------------------------------------------- raster definition
+@pytest.mark.parametrize("delta,B,L", [(0.5, 4, 6), (1.0, 4, 2), (0.5, 2, 3)])
+def test_bruteforce_raster_definition(oracle_lib, delta, B, L):
+    img, mask = tiny_case()
+    got, lg, _ = oracle_lib.reconstruct_reuse(img, mask, 25, delta=delta, block_size=B,
+                                              border=L, log=True)
+    ref, lr = bruteforce_reuse(oracle_lib, img, mask, 25, delta, B, L, 0.7, 0.5)
+    assert np.array_equal(got, ref)
+    assert np.array_equal(lg, lr)
+
+
+# ---------------------------------------------------------------- causality
+@pytest.mark.parametrize("delta", [0.0, 0.5])
+def test_changes_reach_later_blocks_only_through_reuse(oracle_lib, delta):
+    B, L, H, W = 4, 6, 64, 64
+    img, mask = synth.make_image(H, W, 31), synth.quarter_mask(H, W, 32)
+    nbx = W // B
+    jy, jx = 8, 8                                     # block j = (8, 8)
+    img2 = img.copy()
+    ys, xs = np.nonzero(mask[jy * B:(jy + 1) * B, jx * B:(jx + 1) * B])
+    assert ys.size > 0
+    img2[jy * B + ys, jx * B + xs] += 40.0
+    a, _, _ = oracle_lib.reconstruct_reuse(img, mask, 30, delta=delta, block_size=B, border=L)
+    b, _, _ = oracle_lib.reconstruct_reuse(img2, mask, 30, delta=delta, block_size=B, border=L)
+    sees = np.zeros((H // B, nbx), bool)
+    for by in range(H // B):
+        for bx in range(nbx):
+            sees[by, bx] = (by * B - L <= jy * B + B - 1 and jy * B <= by * B + B - 1 + L and
+                            bx * B - L <= jx * B + B - 1 and jx * B <= bx * B + B - 1 + L)
+    first = int(np.flatnonzero(sees.ravel())[0])      # first block in raster order that sees it
+    reached = 0
+    for by in range(H // B):
+        for bx in range(nbx):
+            t = (slice(by * B, by * B + B), slice(bx * B, bx * B + B))
+            same = np.array_equal(a[t], b[t])
+            if sees[by, bx]:
+                continue
+            if by * nbx + bx < first or delta == 0.0:
+                assert same, (by, bx)
+            elif not same:
+                reached += 1
+    if delta > 0.0:
+        assert reached > 0
+
+
+def test_reuse_keeps_known_pixels_and_fully_known_images(oracle_lib):
+    img, mask = synth.workload("small64").inputs()
+    out, _, _ = oracle_lib.reconstruct_reuse(img, mask, 30, delta=0.5)
+    assert np.array_equal(out[mask != 0], img[mask != 0]) and np.all(np.isfinite(out))
+    full, _, _ = oracle_lib.reconstruct_reuse(img, np.ones_like(mask), 20, delta=0.5)
+    assert np.array_equal(full, img)
+
+
+# ---------------------------------------------------------------- planted slips
+MUTANTS = {
+    "column_major_order": ("const int earlier = y < by * B || (y < (by + 1) * B && x < bx * B);",
+                           "const int earlier = x < bx * B || (x < (bx + 1) * B && y < by * B);"),
+    "reuses_current_block": ("const int earlier = y < by * B || (y < (by + 1) * B && x < bx * B);",
+                             "const int earlier = y < by * B || (y < (by + 1) * B && x < (bx + 1) * B);"),
+    "reused_value_from_input": ("reused ? out[(long)y * stride + x] : 0.0;",
+                                "reused ? img[(long)y * stride + x] : 0.0;"),
+    "reused_weight_without_delta": ("reused ? delta * rp[i] : 0.0;", "reused ? rp[i] : 0.0;"),
+    "delta_on_known_pixels": ("w[i] = k ? rp[i] :", "w[i] = k ? delta * rp[i] :"),
+}
+
+PIN_CALLS = [
+    test_delta_zero_is_the_block_independent_method,
+    lambda o: test_first_block_has_nothing_to_reuse(o, 0.5),
+    test_uniform_weight_scaling_is_invisible,
+    lambda o: test_bruteforce_raster_definition(o, 0.5, 4, 6),
+    lambda o: test_changes_reach_later_blocks_only_through_reuse(o, 0.5),
+    test_reuse_keeps_known_pixels_and_fully_known_images,
+]
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_reuse_mutant(tmp_path, name):
+    import oracle
+    before, after = MUTANTS[name]
+    src = open(os.path.join(os.path.dirname(oracle.__file__), "fsr_oracle.c")).read()
+    assert src.count(before) == 1, name
+    path = tmp_path / f"{name}.c"
+    path.write_text(src.replace(before, after))
+    lib = tmp_path / f"lib{name}.so"
+    subprocess.check_call(["gcc", *oracle.CFLAGS, "-w", str(path), "-o", str(lib), "-lm"])
+    saved = (oracle._LIB, oracle._lib)
+    oracle._LIB, oracle._lib = str(lib), None
+    try:
+        caught = 0
+        for call in PIN_CALLS:
+            try:
+                call(oracle)
+            except AssertionError:
+                caught += 1
+    finally:
+        oracle._LIB, oracle._lib = saved
+    assert caught, f"no pin caught mutant {name}"
