@@ -83,6 +83,8 @@ def parse():
                     help="blocks in the oracle's timed sample (default: the whole 1080p frame)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 64-image batched comparison")
+    ap.add_argument("--no-reuse", action="store_true",
+                    help="skip the leg of the sequential variant that reuses reconstructed pixels")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the split-bf16 vs FP32-FFT comparison on the 3840x2160 frame")
     ap.add_argument("--serve-max-batch", type=int, default=2,
@@ -218,6 +220,58 @@ def bench_argmax_ablation(ctx, img32, mask, params, steps: int = 5):
            for tag, ms in best.items()}
     res["speedup_register_over_lds"] = round(res["lds_argmax"]["ms"] / res["register_argmax"]["ms"], 3)
     return res
+
+
+def bench_reuse(ctx, img32, mask, params, delta: float = 0.5, steps: int = 3):
+    """The sequential variant that reuses reconstructed pixels (the original
+    FSR the paper departs from) on the same frame: one launch per wavefront
+    step, eagerly and as a replayed HIP graph, with its quality beside the
+    block-independent result's."""
+    import torch
+
+    import paper_2202_13926_amd as fsr
+    from synth.metrics import psnr
+
+    dev = torch.device("cuda:0")
+    ti = torch.from_numpy(img32).to(dev)
+    tm = torch.from_numpy(mask).to(dev)
+    o = torch.empty_like(ti)
+    ind = torch.empty_like(ti)
+    stream = torch.cuda.current_stream(dev)
+    fsr.fsr_reconstruct(ctx, ti, tm, ind, params, None, stream)
+    fsr.fsr_reconstruct_reuse(ctx, ti, tm, o, params, delta, None, stream)
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    eager_ms = timed(lambda: fsr.fsr_reconstruct_reuse(ctx, ti, tm, o, params, delta, None, stream))
+    side = torch.cuda.Stream(dev)
+    side.wait_stream(stream)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        fsr.fsr_reconstruct_reuse(ctx, ti, tm, o, params, delta, None, side)
+    torch.cuda.synchronize()
+    graph_ms = timed(g.replay)
+    H, W = img32.shape
+    B, L = params.block, params.border
+    nby, nbx, slope = -(-H // B), -(-W // B), (L + B - 1) // B + 1
+    n_steps = (nbx - 1) + slope * (nby - 1) + 1
+    r, miss = o.cpu().numpy(), mask == 0
+    a = ind.cpu().numpy()
+    return {"delta": delta, "wavefront_steps": n_steps,
+            "max_blocks_per_step": min(nby, -(-nbx // slope)),
+            "eager_ms": round(eager_ms, 3), "graph_ms": round(graph_ms, 3),
+            "us_per_step_graph": round(graph_ms * 1e3 / n_steps, 2),
+            "mpx_s_graph": round(img32.size / graph_ms / 1e3, 2),
+            "psnr_missing_db": {"independent": round(psnr(img32, a, miss), 4),
+                                "reuse": round(psnr(img32, r, miss), 4)}}
 
 
 def bench_multiresolution(ctx, steps: int = 5):
@@ -636,6 +690,8 @@ def main():
     }
     res["argmax_ablation"] = bench_argmax_ablation(ctx, img32, mask, params)
     res["multiresolution"] = bench_multiresolution(ctx)
+    if not args.no_reuse:
+        res["reuse_variant"] = bench_reuse(ctx, img32, mask, params)
     if not args.no_batched:
         res["batched"] = bench_batched(ctx)
     if not args.no_precision:

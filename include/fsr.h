@@ -150,6 +150,35 @@ FSR_API fsr_status fsr_reconstruct(fsr_context *ctx, const float *image, const u
                            float *out, int32_t height, int32_t width, int64_t stride,
                            const fsr_params *params, uint16_t *argmax_log, void *stream);
 
+/*
+ * The sequential variant that reuses reconstructed pixels: the original FSR
+ * that Sec. II departs from to make blocks independent.  The result is that
+ * of reconstructing the blocks one after another in raster order (block
+ * row, then block column) where, in the support of a block, a pixel that is
+ * missing but lies in the target of an earlier block takes part with its
+ * reconstructed value and the weight reuse_weight * rho^dist (Eq. 5
+ * scaled); known pixels keep Eq. 5's weight, and the other missing pixels
+ * and those outside the image take no part.
+ *   reuse_weight  in [0, 1] (the original method's publications use 0.5);
+ *                 0 reuses nothing and gives fsr_reconstruct's result
+ *   other arguments as for fsr_reconstruct; `out` is also read: the
+ *                 blocks read earlier blocks' reconstructions from it
+ * Schedule: with r = ceil(L / B), block (by, bx) runs at wavefront step
+ * bx + (r + 1) by, one kernel launch per step; the blocks of a step are
+ * independent and every block a block reuses ran at an earlier step.  That
+ * is (nbx - 1) + (r + 1)(nby - 1) + 1 launches (1,825 for 1920 x 1080 at
+ * B = 4, L = 14), each with at most min(nby, ceil(nbx / (r + 1))) blocks, so
+ * the call is bound by the latency of one block per step rather than by
+ * throughput.  S = 32, FSR_DFT_FP32, no flags (FSR_ERR_UNSUPPORTED
+ * otherwise); a reuse_weight outside [0, 1] or NaN is FSR_ERR_INVALID_ARG.
+ * Asynchronous on `stream`; capturable into a HIP graph under the same
+ * condition as fsr_reconstruct.
+ */
+FSR_API fsr_status fsr_reconstruct_reuse(fsr_context *ctx, const float *image, const uint8_t *mask,
+                                 float *out, int32_t height, int32_t width, int64_t stride,
+                                 const fsr_params *params, float reuse_weight,
+                                 uint16_t *argmax_log, void *stream);
+
 /* ------------------------------------------------------------------ batches */
 
 /* One image of a batch.  Pointers are device memory owned by the caller; the

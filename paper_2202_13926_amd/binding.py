@@ -131,6 +131,8 @@ def load_library(path: str | None = None):
         "fsr_context_create": (ctypes.c_int, [ctypes.POINTER(vp), i32]),
         "fsr_context_destroy": (ctypes.c_int, [vp]),
         "fsr_reconstruct": (ctypes.c_int, [vp, vp, vp, vp, i32, i32, i64, P, vp, vp]),
+        "fsr_reconstruct_reuse": (ctypes.c_int, [vp, vp, vp, vp, i32, i32, i64, P, ctypes.c_float,
+                                                 vp, vp]),
         "fsr_batched_workspace_size": (ctypes.c_int, [i32, ctypes.POINTER(ctypes.c_size_t)]),
         "fsr_reconstruct_batched": (ctypes.c_int, [vp, ctypes.POINTER(fsr_image_desc), i32, P,
                                                    ctypes.POINTER(fsr_batch_schedule), vp,
@@ -279,6 +281,47 @@ def fsr_reconstruct(ctx: Context, image, mask, out, params: fsr_params, argmax_l
         ctx.handle, ctypes.c_void_p(image.data_ptr()), ctypes.c_void_p(mask.data_ptr()),
         ctypes.c_void_p(out.data_ptr()), H, W, stride, ctypes.byref(params), log_ptr,
         _stream_handle(stream, image.device)))
+
+
+def _log_arg(argmax_log, H, W, params):
+    import torch
+    if argmax_log is None:
+        return None
+    n = fsr_num_blocks(H, W, params.block)
+    if (argmax_log.dtype not in (torch.int16, torch.uint16) or not argmax_log.is_cuda
+            or argmax_log.numel() < n * params.iterations or not argmax_log.is_contiguous()):
+        raise FsrError(FSR_ERR_INVALID_ARG, "argmax_log must be a contiguous 16-bit device tensor of N*I entries")
+    return ctypes.c_void_p(argmax_log.data_ptr())
+
+
+def fsr_reconstruct_reuse(ctx: Context, image, mask, out, params: fsr_params, reuse_weight: float,
+                          argmax_log=None, stream=None) -> None:
+    """Enqueue the sequential variant that reuses reconstructed pixels (one
+    launch per wavefront step) on ``stream``."""
+    H, W, stride = _image_args(image, mask, out)
+    log_ptr = _log_arg(argmax_log, H, W, params)
+    _check(load_library().fsr_reconstruct_reuse(
+        ctx.handle, ctypes.c_void_p(image.data_ptr()), ctypes.c_void_p(mask.data_ptr()),
+        ctypes.c_void_p(out.data_ptr()), H, W, stride, ctypes.byref(params), float(reuse_weight),
+        log_ptr, _stream_handle(stream, image.device)))
+
+
+def reconstruct_reuse(image, mask, params: fsr_params | None = None, reuse_weight: float = 0.5,
+                      ctx: Context | None = None, log: bool = False, stream=None):
+    """Allocate the output (and the argmax log) and run
+    :func:`fsr_reconstruct_reuse`.  Returns ``out`` or ``(out, log)``."""
+    import torch
+    params = params or make_params()
+    ctx = ctx or Context(image.device.index or 0)
+    out = torch.empty_like(image)
+    lg = None
+    if log:
+        n = fsr_num_blocks(image.shape[0], image.shape[1], params.block)
+        lg = torch.empty((n, max(params.iterations, 1)), dtype=torch.int16, device=image.device)
+    fsr_reconstruct_reuse(ctx, image, mask, out, params, reuse_weight, lg, stream)
+    if log:
+        return out, lg[:, :params.iterations]
+    return out
 
 
 def reconstruct(image, mask, params: fsr_params | None = None, ctx: Context | None = None,

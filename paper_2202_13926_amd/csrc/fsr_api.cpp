@@ -377,6 +377,39 @@ fsr_status fsr_context_destroy(fsr_context* ctx) {
     return FSR_OK;
 }
 
+}  // extern "C"
+
+namespace fsr {
+
+// The launch description of one image; the caller has validated every argument.
+static PlainLaunch plain_launch(const float* image, const uint8_t* mask, float* out, int32_t height,
+                                int32_t width, int64_t stride, const fsr_params* params,
+                                uint16_t* argmax_log) {
+    PlainLaunch p{};
+    p.img.image = image;
+    p.img.mask = mask;
+    p.img.out = out;
+    p.img.argmax_log = argmax_log;
+    p.img.height = height;
+    p.img.width = width;
+    p.img.stride = stride;
+    p.img.iterations = params->iterations;
+    p.img.nbx = (width + params->block - 1) / params->block;
+    p.img.block_begin = 0;
+    p.block = params->block;
+    p.border = params->border;
+    p.support = params->block + 2 * params->border;
+    p.gamma = params->gamma;
+    p.n_blocks = fsr_num_blocks(height, width, params->block);
+    p.dft = params->dft == FSR_DFT_SPLIT_BF16 ? 1 : 0;
+    p.lds_argmax = (params->flags & FSR_FLAG_LDS_ARGMAX) ? 1 : 0;
+    return p;
+}
+
+}  // namespace fsr
+
+extern "C" {
+
 fsr_status fsr_reconstruct(fsr_context* ctx, const float* image, const uint8_t* mask, float* out,
                            int32_t height, int32_t width, int64_t stride, const fsr_params* params,
                            uint16_t* argmax_log, void* stream) {
@@ -400,28 +433,42 @@ fsr_status fsr_reconstruct(fsr_context* ctx, const float* image, const uint8_t* 
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     hipError_t ce = hipStreamIsCapturing((hipStream_t)stream, &cap);
     if (ce != hipSuccess) return hip_fail(ce, "hipStreamIsCapturing");
-    PlainLaunch p{};
+    PlainLaunch p = plain_launch(image, mask, out, height, width, stride, params, argmax_log);
     if ((st = context_tables(ctx, S, params->rho, &p.tab, cap == hipStreamCaptureStatusNone)) != FSR_OK)
         return st;
-    p.img.image = image;
-    p.img.mask = mask;
-    p.img.out = out;
-    p.img.argmax_log = argmax_log;
-    p.img.height = height;
-    p.img.width = width;
-    p.img.stride = stride;
-    p.img.iterations = params->iterations;
-    p.img.nbx = (width + params->block - 1) / params->block;
-    p.img.block_begin = 0;
-    p.block = params->block;
-    p.border = params->border;
-    p.support = S;
-    p.gamma = params->gamma;
-    p.n_blocks = fsr_num_blocks(height, width, params->block);
-    p.dft = params->dft == FSR_DFT_SPLIT_BF16 ? 1 : 0;
-    p.lds_argmax = (params->flags & FSR_FLAG_LDS_ARGMAX) ? 1 : 0;
     hipError_t e = launch_plain(p, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "launch of the reconstruction kernel");
+    return FSR_OK;
+}
+
+fsr_status fsr_reconstruct_reuse(fsr_context* ctx, const float* image, const uint8_t* mask, float* out,
+                                 int32_t height, int32_t width, int64_t stride, const fsr_params* params,
+                                 float reuse_weight, uint16_t* argmax_log, void* stream) {
+    if (!ctx) return fail(FSR_ERR_INVALID_ARG, "context is NULL");
+    fsr_status st = validate_params(params);
+    if (st != FSR_OK) return st;
+    if (!(reuse_weight >= 0.0f && reuse_weight <= 1.0f))
+        return fail(FSR_ERR_INVALID_ARG, "reuse_weight must lie in [0, 1] (got %g)", (double)reuse_weight);
+    if ((st = check_supported(params)) != FSR_OK) return st;
+    if ((st = validate_image(image, mask, out, height, width, stride, params->block)) != FSR_OK)
+        return st;
+    const int S = params->block + 2 * params->border;
+    if (S != kS || params->dft != FSR_DFT_FP32 || params->flags != 0)
+        return fail(FSR_ERR_UNSUPPORTED, "the reuse variant runs at S = 32 with FSR_DFT_FP32 and no flags "
+                                         "only (got S = %d)", S);
+    if (reuse_steps(height, width, params->block, params->border) > 0x7fffffff)
+        return fail(FSR_ERR_UNSUPPORTED, "more than 2^31-1 wavefront steps");
+
+    DeviceGuard g(ctx->device);
+    if (g.error() != hipSuccess) return hip_fail(g.error(), "hipSetDevice");
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    hipError_t ce = hipStreamIsCapturing((hipStream_t)stream, &cap);
+    if (ce != hipSuccess) return hip_fail(ce, "hipStreamIsCapturing");
+    PlainLaunch p = plain_launch(image, mask, out, height, width, stride, params, argmax_log);
+    if ((st = context_tables(ctx, S, params->rho, &p.tab, cap == hipStreamCaptureStatusNone)) != FSR_OK)
+        return st;
+    hipError_t e = launch_reuse(p, reuse_weight, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "launch of the reuse-variant kernels");
     return FSR_OK;
 }
 

@@ -121,6 +121,8 @@ struct BlockJob {
     int64_t stride;
     int32_t by, bx;
     int32_t iterations;
+    // reuse variant only: weight factor of reused pixels (0 reuses nothing)
+    float delta = 0.0f;
 };
 
 // Block `blk` of a one-image launch.
@@ -163,7 +165,12 @@ __device__ __forceinline__ uint2 better_pair(uint2 a, uint2 b) {
 // kernel).  Its per-block values are then made opaque, so that the compiler
 // does not hoist the table loads and lane constants out of the caller's loop
 // and keep them live across every block.
-template <int kDft, int kArgmax, bool kPersistent>
+// kReuse: the sequential variant (the original FSR that Sec. II departs
+// from).  A support pixel that is missing but lies in the target of a block
+// earlier in raster order takes part with its reconstruction, read from
+// jb.out, and the weight jb.delta rho^dist; the caller guarantees that those
+// blocks have finished.
+template <int kDft, int kArgmax, bool kPersistent, bool kReuse = false>
 __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int L, float gamma,
                                                   const BlockTables& tab_in, float* lds,
                                                   uint2* argmax_lds = nullptr) {
@@ -195,9 +202,19 @@ __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int
         const uint8_t k = in ? kraw : (uint8_t)0;
         const float f = fraw;
         const float w = k ? rp : 0.0f;
-        any_known |= ballot(k != 0);
-        xr[s] = k ? f : 0.0f;
-        wr[s] = w;
+        if constexpr (kReuse) {
+            // earlier targets: the rows above this target, and this target's
+            // rows left of it
+            const bool earlier = m < L || (m < L + B && c < L);
+            const bool reused = in && !k && earlier && jb.delta > 0.0f;
+            any_known |= ballot(k != 0 || reused);
+            xr[s] = k ? f : reused ? (float)jb.out[off] : 0.0f;
+            wr[s] = reused ? jb.delta * rp : w;
+        } else {
+            any_known |= ballot(k != 0);
+            xr[s] = k ? f : 0.0f;
+            wr[s] = w;
+        }
     }
 
     // ---- target pixel owned by this lane (lanes 0 .. B*B-1)

@@ -51,6 +51,9 @@ struct PlainLaunch {
 };
 
 hipError_t launch_plain(const PlainLaunch& p, hipStream_t stream);
+// The reuse variant at S = 32 (fsr_reuse.hip): one launch per wavefront step.
+hipError_t launch_reuse(const PlainLaunch& p, float delta, hipStream_t stream);
+int64_t reuse_steps(int32_t height, int32_t width, int32_t block, int32_t border);
 hipError_t launch_plain_sg(const PlainLaunch& p, hipStream_t stream);   // S = 8, 16, 24
 
 }  // namespace fsr

@@ -1,0 +1,57 @@
+// fsr_reuse.hip -- the sequential variant that reuses reconstructed pixels
+// (the original FSR that Sec. II departs from), at S = 32.
+//
+// The variant is defined by raster order: block (by, bx) sees the
+// reconstructions of every earlier block whose target meets its support.
+// With r = ceil(L / B) those are the blocks of rows by - r .. by - 1 and
+// columns bx - r .. bx + r, and those of row by and columns bx - r .. bx - 1.
+// Giving block (by, bx) the step t = bx + (r + 1) by puts every such block
+// at a smaller step, and two blocks of one step lie at least r + 1 block
+// columns apart, so that neither's target meets the other's support.  One
+// launch per step (a wavefront schedule) therefore gives exactly the raster
+// result, with the stream's order between launches as the only
+// synchronisation.
+#include <algorithm>
+
+#include "fsr_block.h"
+
+namespace fsr {
+
+// Blocks (by, step - slope * by) for by = by_lo + blockIdx.x; the host sizes
+// the grid so that every bx lies in [0, nbx).
+__global__ __launch_bounds__(64) void fsr_reuse_s32(PlainLaunch p, float delta, int32_t step,
+                                                    int32_t by_lo, int32_t slope) {
+    __shared__ __align__(16) float lds[kLdsFloats];
+    const int by = by_lo + (int)blockIdx.x;
+    const int bx = step - slope * by;
+    BlockJob jb = plain_job(p, (int64_t)by * p.img.nbx + bx);
+    jb.delta = delta;
+    reconstruct_block<kDftFft32, kArgmaxWave, false, true>(jb, p.block, p.border, p.gamma, p.tab, lds);
+}
+
+int64_t reuse_steps(int32_t height, int32_t width, int32_t block, int32_t border) {
+    const int64_t nby = (height + block - 1) / block, nbx = (width + block - 1) / block;
+    const int64_t slope = (border + block - 1) / block + 1;
+    return (nbx - 1) + slope * (nby - 1) + 1;
+}
+
+hipError_t launch_reuse(const PlainLaunch& p, float delta, hipStream_t stream) {
+    const int32_t B = p.block;
+    const int64_t nbx = p.img.nbx, nby = (p.img.height + B - 1) / B;
+    const int64_t slope = (p.border + B - 1) / B + 1;
+    const int64_t steps = reuse_steps(p.img.height, p.img.width, B, p.border);
+    for (int64_t t = 0; t < steps; ++t) {
+        // by in [ceil((t - (nbx - 1)) / slope), floor(t / slope)] within [0, nby)
+        const int64_t over = t - (nbx - 1);
+        const int64_t lo = over > 0 ? (over + slope - 1) / slope : 0;
+        const int64_t hi = std::min<int64_t>(nby - 1, t / slope);
+        if (hi < lo) continue;   // no block at this step (possible when slope > nbx)
+        hipLaunchKernelGGL(fsr_reuse_s32, dim3((unsigned)(hi - lo + 1)), dim3(64), 0, stream, p, delta,
+                           (int32_t)t, (int32_t)lo, (int32_t)slope);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace fsr

@@ -81,6 +81,28 @@ def test_reconstruct_validates_before_touching_the_device(lib):
     assert _call(lib, fake_ctx, img, msk, out, 8, 8, 8, lds_bf16) == binding.FSR_ERR_UNSUPPORTED
 
 
+def test_reuse_variant_validates_before_touching_the_device(lib):
+    p = fsr.make_params()
+    fake_ctx = ctypes.c_void_p(0x1000)        # never dereferenced: validation fails first
+    img, msk, out = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x20000000), ctypes.c_void_p(0x40000000)
+
+    def call(ctx, i, m, o, H, W, stride, params, delta):
+        return lib.fsr_reconstruct_reuse(ctx, i, m, o, H, W, stride, ctypes.byref(params), delta,
+                                         None, None)
+
+    assert call(None, img, msk, out, 8, 8, 8, p, 0.5) == binding.FSR_ERR_INVALID_ARG
+    assert call(fake_ctx, None, msk, out, 8, 8, 8, p, 0.5) == binding.FSR_ERR_INVALID_ARG
+    assert call(fake_ctx, img, msk, out, 8, 8, 7, p, 0.5) == binding.FSR_ERR_INVALID_ARG
+    assert call(fake_ctx, img, msk, ctypes.c_void_p(0x10000 + 64), 8, 8, 8, p, 0.5) == binding.FSR_ERR_INVALID_ARG
+    for bad in (-0.25, 1.5, float("nan")):
+        assert call(fake_ctx, img, msk, out, 8, 8, 8, p, bad) == binding.FSR_ERR_INVALID_ARG
+    # S = 32 with the FP32 FFTs and no flags only
+    for p_other in (fsr.make_params(block=4, border=6), fsr.make_params(dft=fsr.FSR_DFT_SPLIT_BF16),
+                    fsr.make_params(flags=fsr.FSR_FLAG_LDS_ARGMAX)):
+        assert call(fake_ctx, img, msk, out, 8, 8, 8, p_other, 0.5) == binding.FSR_ERR_UNSUPPORTED
+    assert "reuse" in lib.fsr_last_error_message().decode()
+
+
 def test_missing_library_fails_loudly(tmp_path):
     with pytest.raises(fsr.FsrError):
         binding.load_library(str(tmp_path / "nope.so"))

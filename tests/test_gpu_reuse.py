@@ -1,0 +1,183 @@
+"""The sequential variant that reuses reconstructed pixels (GPU) against the
+oracle's sequential raster definition.
+
+fsr_reconstruct_reuse runs the blocks in a wavefront schedule, one launch
+per step; its result must be that of raster order.
+
+The reuse chain carries any difference in a block's decisions into every
+later block that reuses it, and a near-tied argmax (objectives within FP32
+rounding of each other) is decided by rounding.  The oracle itself, given
+an input changed by a relative 1e-6, moves that way in some regimes
+(test_oracle_reuse.py shows which).  So:
+  * in the regimes where the oracle does not move, the acceptance is that of
+    the block-independent path: known pixels bitwise, |gpu - oracle| <= 1
+    code value on >= 99.9 % of the reconstructed pixels, PSNR gap <= 0.05 dB
+    and >= 99 % argmax agreement, the oracle deciding at the kernel's
+    precision;
+  * in the others (the quarter mask at I = 100) the GPU must stay within the
+    oracle's own spread under such a change: known pixels bitwise, the share
+    within 1 code value no more than 0.1 below the worst of three perturbed
+    oracle runs, the PSNR gap <= 0.05 dB (or twice the oracle's own gap).
+    The argmax agreement is printed, not asserted: there it only tells how
+    early the first near-tie fell, which the oracle's own runs show to vary
+    (0.68 to 0.75 and below).
+
+At full size (1920 x 1080) the oracle runs on a top-left crop of the frame;
+a block of the crop whose support lies inside it and whose reused blocks
+are all such blocks sees exactly what it sees in the full frame, so those
+blocks are compared.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth.metrics import parity_report
+from tests.test_oracle_reuse import STABLE_CASES, exact_blocks, perturbed_spread
+
+torch = pytest.importorskip("torch")
+import paper_2202_13926_amd as fsr  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+KERNEL = oracle.DECISION_KERNEL
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return fsr.Context(0)
+
+
+def announce(name):
+    print(f"\n[gpu case] {name}", flush=True)
+
+
+def assert_parity(rep, name):
+    print(f"[parity] {name}: {rep}", flush=True)
+    assert rep["known_bitwise"]
+    assert rep["frac_le_1"] >= 0.999
+    assert rep["psnr_gap"] <= 0.05
+    if "argmax_agree" in rep:
+        assert rep["argmax_agree"] >= 0.99
+
+
+def run(ctx, img, mask, params, delta, reuse=True):
+    ti = torch.from_numpy(np.ascontiguousarray(img, np.float32)).to(DEV)
+    tm = torch.from_numpy(np.ascontiguousarray(mask, np.uint8)).to(DEV)
+    out = torch.full_like(ti, -7.0)
+    n = fsr.fsr_num_blocks(img.shape[0], img.shape[1], params.block)
+    lg = torch.full((n, max(params.iterations, 1)), -1, dtype=torch.int16, device=DEV)
+    if reuse:
+        fsr.fsr_reconstruct_reuse(ctx, ti, tm, out, params, delta, lg)
+    else:
+        fsr.fsr_reconstruct(ctx, ti, tm, out, params, lg)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), lg.cpu().numpy().view(np.uint16)[:, :params.iterations]
+
+
+def assert_within_spread(rep, spread, name):
+    print(f"[parity] {name}: {rep}\n[spread] oracle under a 1e-6 input change: {spread}", flush=True)
+    assert rep["known_bitwise"]
+    assert rep["frac_le_1"] >= spread["frac_le_1"] - 0.1
+    assert rep["psnr_gap"] <= max(0.05, 2 * spread["psnr_gap"])
+
+
+@pytest.mark.parametrize("H,W,mk,B,L,iters,delta", STABLE_CASES)
+def test_stable_cases_exhaustive(ctx, H, W, mk, B, L, iters, delta):
+    announce(f"reuse {H}x{W} {mk} B={B} L={L} I={iters} delta={delta}: every pixel and log entry")
+    img = synth.make_image(H, W, 2100 + H).astype(np.float32)
+    mask = synth.make_mask(mk, H, W, 2200 + W)
+    p = fsr.make_params(block=B, border=L, iterations=iters)
+    g, gl = run(ctx, img, mask, p, delta)
+    o, ol, _ = oracle.reconstruct_reuse(img.astype(np.float64), mask, iters, delta=delta,
+                                        block_size=B, border=L, log=True, decision=KERNEL)
+    assert_parity(parity_report(img, mask, g, o, gl, ol), f"reuse {H}x{W} B={B} I={iters}")
+
+
+@pytest.mark.parametrize("B,L", [(4, 14), (2, 15)])
+def test_chaotic_cases_within_the_oracle_spread(ctx, B, L):
+    announce(f"reuse 64x64 quarter B={B} L={L} I=100 delta=0.5: within the oracle's own spread")
+    img = synth.make_image(64, 64, 2164).astype(np.float32)
+    mask = synth.make_mask("quarter", 64, 64, 2264)
+    p = fsr.make_params(block=B, border=L, iterations=100)
+    g, gl = run(ctx, img, mask, p, 0.5)
+    o, ol, spread = perturbed_spread(oracle, img.astype(np.float64), mask, 100, 0.5, B, L)
+    assert_within_spread(parity_report(img, mask, g, o, gl, ol), spread, f"reuse 64x64 B={B}")
+
+
+def test_delta_zero_is_the_block_independent_result(ctx):
+    announce("fhd_quarter, delta = 0: bitwise the one-launch result")
+    w = synth.workload("fhd_quarter")
+    img, mask = w.inputs()
+    p = fsr.make_params()
+    a, la = run(ctx, img, mask, p, 0.0)
+    b, lb = run(ctx, img, mask, p, 0.0, reuse=False)
+    assert np.array_equal(a, b) and np.array_equal(la, lb)
+
+
+def test_full_frame_against_the_oracle_on_a_crop(ctx):
+    announce("fhd_quarter full frame, delta = 0.5; oracle on the top-left 48 x 800 crop")
+    w = synth.workload("fhd_quarter")
+    img, mask = w.inputs()
+    img32 = img.astype(np.float32)
+    p = fsr.make_params()
+    g, gl = run(ctx, img32, mask, p, 0.5)
+    assert np.array_equal(g[mask != 0], img32[mask != 0]) and np.all(np.isfinite(g))
+    Hc, Wc, B = 48, 800, 4
+    ok = exact_blocks(Hc, Wc, w.height, w.width, B, 14)
+    assert ok.sum() > 1000
+    o, ol, spread = perturbed_spread(oracle, img32[:Hc, :Wc].astype(np.float64), mask[:Hc, :Wc], 100,
+                                     0.5, B, 14, sel=ok)
+    sel = np.kron(ok, np.ones((B, B), bool))[:Hc, :Wc]
+    nbx_full, nbx_crop = w.width // B, Wc // B
+    ys, xs = np.nonzero(ok)
+    rep = parity_report(img32[:Hc, :Wc][sel], mask[:Hc, :Wc][sel], g[:Hc, :Wc][sel], o[sel],
+                        gl[ys * nbx_full + xs], ol[ys * nbx_crop + xs])
+    assert_within_spread(rep, spread, f"fhd crop, {int(ok.sum())} exact blocks")
+
+
+def test_deterministic_with_quality_report(ctx):
+    announce("fhd_quarter reuse twice: bitwise equal; PSNR against the block-independent path")
+    w = synth.workload("fhd_quarter")
+    img, mask = w.inputs()
+    p = fsr.make_params()
+    a, la = run(ctx, img, mask, p, 0.5)
+    b, lb = run(ctx, img, mask, p, 0.5)
+    assert np.array_equal(a, b) and np.array_equal(la, lb)
+    ind, _ = run(ctx, img, mask, p, 0.0, reuse=False)
+    from synth.metrics import psnr
+    print(f"[quality] psnr independent {psnr(img, ind):.3f} reuse(0.5) {psnr(img, a):.3f}", flush=True)
+
+
+def test_reuse_call_replays_in_a_graph(ctx):
+    announce("graph capture of the reuse call (150 x 200, delta = 0.5)")
+    img = synth.make_image(150, 200, 2301).astype(np.float32)
+    mask = synth.make_mask("quarter", 150, 200, 2302)
+    p = fsr.make_params(iterations=80)
+    ref, ref_log = run(ctx, img, mask, p, 0.5)             # eager; builds the tables
+    ti = torch.from_numpy(img).to(DEV)
+    tm = torch.from_numpy(mask).to(DEV)
+    out = torch.full_like(ti, -1.0)
+    n = fsr.fsr_num_blocks(150, 200, 4)
+    log = torch.full((n, p.iterations), -1, dtype=torch.int16, device=DEV)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fsr.fsr_reconstruct_reuse(ctx, ti, tm, out, p, 0.5, log)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fsr.fsr_reconstruct_reuse(ctx, ti, tm, out, p, 0.5, log)
+    other = synth.make_image(40, 64, 2303).astype(np.float32)
+    other_mask = synth.make_mask("uniform:0.4", 40, 64, 2304)
+    for _ in range(3):
+        out.fill_(-5.0)
+        log.fill_(-3)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), ref)
+        assert np.array_equal(log.cpu().numpy().view(np.uint16), ref_log)
+        run(ctx, other, other_mask, p, 0.5)                # eager work between replays
