@@ -181,3 +181,75 @@ def test_reuse_call_replays_in_a_graph(ctx):
         assert np.array_equal(out.cpu().numpy(), ref)
         assert np.array_equal(log.cpu().numpy().view(np.uint16), ref_log)
         run(ctx, other, other_mask, p, 0.5)                # eager work between replays
+
+
+# ---------------------------------------------------------------- edge cases
+def run_strided(ctx, img, mask, params, delta, stride):
+    H, W = img.shape
+    bi = torch.zeros((H, stride), dtype=torch.float32, device=DEV)
+    bm = torch.zeros((H, stride), dtype=torch.uint8, device=DEV)
+    bi[:, :W] = torch.from_numpy(np.ascontiguousarray(img, np.float32))
+    bm[:, :W] = torch.from_numpy(np.ascontiguousarray(mask, np.uint8))
+    out = torch.full((H, stride), -7.0, dtype=torch.float32, device=DEV)
+    n = fsr.fsr_num_blocks(H, W, params.block)
+    lg = torch.full((n, max(params.iterations, 1)), -1, dtype=torch.int16, device=DEV)
+    fsr.fsr_reconstruct_reuse(ctx, bi[:, :W], bm[:, :W], out[:, :W], params, delta, lg)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    assert np.all(o[:, W:] == -7.0)                        # nothing beyond the width is written
+    return o[:, :W], lg.cpu().numpy().view(np.uint16)[:, :params.iterations]
+
+
+def oracle_reuse(img, mask, p, delta):
+    return oracle.reconstruct_reuse(img.astype(np.float64), mask, p.iterations, delta=delta,
+                                    block_size=p.block, border=p.border, log=True, decision=KERNEL)
+
+
+@pytest.mark.parametrize("H,W", [(1, 1), (3, 5), (4, 4), (33, 1), (5, 47)])
+def test_tiny_frames(ctx, H, W):
+    announce(f"reuse tiny {H}x{W}, I = 30")
+    img = synth.make_image(H, W, 2400 + H * W).astype(np.float32)
+    mask = synth.make_mask("quarter", H, W, 2500 + H * W)
+    p = fsr.make_params(iterations=30)
+    g, gl = run(ctx, img, mask, p, 0.5)
+    o, ol, _ = oracle_reuse(img, mask, p, 0.5)
+    assert_parity(parity_report(img, mask, g, o, gl, ol), f"reuse tiny {H}x{W}")
+
+
+def test_row_stride_wider_than_the_frame(ctx):
+    announce("reuse 50x70 quarter I = 40 with row stride 96")
+    img = synth.make_image(50, 70, 2601).astype(np.float32)
+    mask = synth.make_mask("quarter", 50, 70, 2602)
+    p = fsr.make_params(iterations=40)
+    g, gl = run_strided(ctx, img, mask, p, 0.5, 96)
+    a, la = run(ctx, img, mask, p, 0.5)
+    assert np.array_equal(g, a) and np.array_equal(gl, la)
+    o, ol, _ = oracle_reuse(img, mask, p, 0.5)
+    assert_parity(parity_report(img, mask, g, o, gl, ol), "reuse strided 50x70")
+
+
+def test_zero_iterations_and_fully_known(ctx):
+    announce("reuse: I = 0 gives known pixels and zeros; a fully known frame is unchanged")
+    img = synth.make_image(40, 36, 2701).astype(np.float32)
+    mask = synth.make_mask("quarter", 40, 36, 2702)
+    g, _ = run(ctx, img, mask, fsr.make_params(iterations=0), 0.5)
+    assert np.array_equal(g[mask != 0], img[mask != 0]) and np.all(g[mask == 0] == 0.0)
+    full, _ = run(ctx, img, np.ones_like(mask), fsr.make_params(iterations=20), 0.5)
+    assert np.array_equal(full, img)
+
+
+def test_no_known_pixel_at_all(ctx):
+    """The first block has nothing to work with (no iteration, log 0xFFFF);
+    every later one reuses the zeros written before it, so its residual is
+    exactly zero, every objective ties and the smallest bin, 0, is picked
+    with p = 0: the whole frame is 0."""
+    announce("reuse 24x28 with an empty mask")
+    img = synth.make_image(24, 28, 2801).astype(np.float32)
+    mask = np.zeros((24, 28), np.uint8)
+    p = fsr.make_params(iterations=25)
+    g, gl = run(ctx, img, mask, p, 0.5)
+    o, ol, n_empty = oracle_reuse(img, mask, p, 0.5)
+    assert n_empty == 1 and np.all(o == 0.0)
+    assert np.all(g == 0.0)
+    assert np.array_equal(gl, ol)
+    assert np.all(gl[0] == 0xFFFF) and np.all(gl[1:] == 0)
