@@ -259,6 +259,18 @@ def bench_reuse(ctx, img32, mask, params, delta: float = 0.5, steps: int = 3):
         fsr.fsr_reconstruct_reuse(ctx, ti, tm, o, params, delta, None, side)
     torch.cuda.synchronize()
     graph_ms = timed(g.replay)
+    # frames of one size in one call: one launch per step takes every frame's blocks
+    frames = {}
+    for n in (4, 16, 64):
+        imgs = torch.stack([ti, ti.flip(0), ti.flip(1), ti.flip(0, 1)] * (n // 4)).contiguous()
+        masks = torch.stack([tm, tm.flip(1), tm.flip(0), tm.flip(0, 1)] * (n // 4)).contiguous()
+        outs = torch.empty_like(imgs)
+        fsr.fsr_reconstruct_reuse_frames(ctx, imgs, masks, outs, params, delta, None, stream)
+        torch.cuda.synchronize()
+        ms = timed(lambda: fsr.fsr_reconstruct_reuse_frames(ctx, imgs, masks, outs, params, delta, None, stream))
+        frames[f"frames_{n}"] = {"ms": round(ms, 3), "ms_per_frame": round(ms / n, 3),
+                                 "mpx_s": round(n * img32.size / ms / 1e3, 2)}
+        del imgs, masks, outs
     H, W = img32.shape
     B, L = params.block, params.border
     nby, nbx, slope = -(-H // B), -(-W // B), (L + B - 1) // B + 1
@@ -269,7 +281,7 @@ def bench_reuse(ctx, img32, mask, params, delta: float = 0.5, steps: int = 3):
             "max_blocks_per_step": min(nby, -(-nbx // slope)),
             "eager_ms": round(eager_ms, 3), "graph_ms": round(graph_ms, 3),
             "us_per_step_graph": round(graph_ms * 1e3 / n_steps, 2),
-            "mpx_s_graph": round(img32.size / graph_ms / 1e3, 2),
+            "mpx_s_graph": round(img32.size / graph_ms / 1e3, 2), **frames,
             "psnr_missing_db": {"independent": round(psnr(img32, a, miss), 4),
                                 "reuse": round(psnr(img32, r, miss), 4)}}
 

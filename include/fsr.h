@@ -179,6 +179,26 @@ FSR_API fsr_status fsr_reconstruct_reuse(fsr_context *ctx, const float *image, c
                                  const fsr_params *params, float reuse_weight,
                                  uint16_t *argmax_log, void *stream);
 
+/*
+ * fsr_reconstruct_reuse over n_frames frames of one size (a video's frames),
+ * each reconstructed on its own as above; one launch per wavefront step
+ * takes that step's blocks of every frame, which fills the device where one
+ * frame's at most min(nby, ceil(nbx / (r + 1))) blocks per step cannot.
+ *   image, mask, out  frame f starts f * frame_stride elements after frame 0;
+ *                     rows `stride` elements apart within a frame;
+ *                     frame_stride >= (height - 1) * stride + width (frames
+ *                     do not overlap)
+ *   argmax_log        NULL, or n_frames x N x I uint16, frame-major
+ *   n_frames          1 .. 65535
+ * Every frame's output and log are bitwise those of fsr_reconstruct_reuse on
+ * it alone.  Errors and stream behaviour as for fsr_reconstruct_reuse.
+ */
+FSR_API fsr_status fsr_reconstruct_reuse_frames(fsr_context *ctx, const float *image,
+                                        const uint8_t *mask, float *out, int32_t n_frames,
+                                        int32_t height, int32_t width, int64_t stride,
+                                        int64_t frame_stride, const fsr_params *params,
+                                        float reuse_weight, uint16_t *argmax_log, void *stream);
+
 /* ------------------------------------------------------------------ batches */
 
 /* One image of a batch.  Pointers are device memory owned by the caller; the

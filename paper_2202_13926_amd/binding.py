@@ -133,6 +133,8 @@ def load_library(path: str | None = None):
         "fsr_reconstruct": (ctypes.c_int, [vp, vp, vp, vp, i32, i32, i64, P, vp, vp]),
         "fsr_reconstruct_reuse": (ctypes.c_int, [vp, vp, vp, vp, i32, i32, i64, P, ctypes.c_float,
                                                  vp, vp]),
+        "fsr_reconstruct_reuse_frames": (ctypes.c_int, [vp, vp, vp, vp, i32, i32, i32, i64, i64, P,
+                                                        ctypes.c_float, vp, vp]),
         "fsr_batched_workspace_size": (ctypes.c_int, [i32, ctypes.POINTER(ctypes.c_size_t)]),
         "fsr_reconstruct_batched": (ctypes.c_int, [vp, ctypes.POINTER(fsr_image_desc), i32, P,
                                                    ctypes.POINTER(fsr_batch_schedule), vp,
@@ -304,6 +306,32 @@ def fsr_reconstruct_reuse(ctx: Context, image, mask, out, params: fsr_params, re
         ctx.handle, ctypes.c_void_p(image.data_ptr()), ctypes.c_void_p(mask.data_ptr()),
         ctypes.c_void_p(out.data_ptr()), H, W, stride, ctypes.byref(params), float(reuse_weight),
         log_ptr, _stream_handle(stream, image.device)))
+
+
+def fsr_reconstruct_reuse_frames(ctx: Context, images, masks, outs, params: fsr_params,
+                                 reuse_weight: float, argmax_log=None, stream=None) -> None:
+    """The reuse variant over the frames of 3-D (n, H, W) device tensors that
+    share one frame stride and one row stride (e.g. contiguous, or views of
+    wider buffers); ``argmax_log`` is None or n x N x I 16-bit."""
+    import torch
+    if images.dim() != 3 or masks.shape != images.shape or outs.shape != images.shape:
+        raise FsrError(FSR_ERR_INVALID_ARG, "images, masks and outs must be 3-D of equal shape")
+    n, H, W = images.shape
+    H2, W2, stride = _image_args(images[0], masks[0], outs[0])
+    fstrides = {t.stride(0) if n > 1 else 0 for t in (images, masks, outs)}
+    if len(fstrides) != 1:
+        raise FsrError(FSR_ERR_INVALID_ARG, "images, masks and outs need one frame stride")
+    log_ptr = None
+    if argmax_log is not None:
+        nb = fsr_num_blocks(H, W, params.block)
+        if (argmax_log.dtype not in (torch.int16, torch.uint16) or not argmax_log.is_cuda
+                or argmax_log.numel() < n * nb * params.iterations or not argmax_log.is_contiguous()):
+            raise FsrError(FSR_ERR_INVALID_ARG, "argmax_log must be a contiguous 16-bit device tensor of n*N*I entries")
+        log_ptr = ctypes.c_void_p(argmax_log.data_ptr())
+    _check(load_library().fsr_reconstruct_reuse_frames(
+        ctx.handle, ctypes.c_void_p(images.data_ptr()), ctypes.c_void_p(masks.data_ptr()),
+        ctypes.c_void_p(outs.data_ptr()), n, H, W, stride, fstrides.pop(), ctypes.byref(params),
+        float(reuse_weight), log_ptr, _stream_handle(stream, images.device)))
 
 
 def reconstruct_reuse(image, mask, params: fsr_params | None = None, reuse_weight: float = 0.5,

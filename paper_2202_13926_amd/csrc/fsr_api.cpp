@@ -441,9 +441,16 @@ fsr_status fsr_reconstruct(fsr_context* ctx, const float* image, const uint8_t* 
     return FSR_OK;
 }
 
-fsr_status fsr_reconstruct_reuse(fsr_context* ctx, const float* image, const uint8_t* mask, float* out,
-                                 int32_t height, int32_t width, int64_t stride, const fsr_params* params,
-                                 float reuse_weight, uint16_t* argmax_log, void* stream) {
+}  // extern "C"
+
+namespace fsr {
+
+// The reuse variant over n_frames frames of one size, frame_stride elements
+// apart (1 and 0 for a single frame); validates everything first.
+static fsr_status reuse_call(fsr_context* ctx, const float* image, const uint8_t* mask, float* out,
+                             int32_t n_frames, int32_t height, int32_t width, int64_t stride,
+                             int64_t frame_stride, const fsr_params* params, float reuse_weight,
+                             uint16_t* argmax_log, void* stream) {
     if (!ctx) return fail(FSR_ERR_INVALID_ARG, "context is NULL");
     fsr_status st = validate_params(params);
     if (st != FSR_OK) return st;
@@ -452,6 +459,19 @@ fsr_status fsr_reconstruct_reuse(fsr_context* ctx, const float* image, const uin
     if ((st = check_supported(params)) != FSR_OK) return st;
     if ((st = validate_image(image, mask, out, height, width, stride, params->block)) != FSR_OK)
         return st;
+    if (n_frames < 1 || n_frames > 65535)
+        return fail(FSR_ERR_INVALID_ARG, "n_frames must lie in [1, 65535] (got %d)", n_frames);
+    if (n_frames > 1) {
+        const int64_t frame_extent = (int64_t)(height - 1) * stride + width;
+        if (frame_stride < frame_extent)
+            return fail(FSR_ERR_INVALID_ARG, "frame_stride %lld is smaller than one frame (%lld elements)",
+                        (long long)frame_stride, (long long)frame_extent);
+        if (frame_stride > ((int64_t)1 << 40) / n_frames) return fail(FSR_ERR_INVALID_ARG, "frames too large");
+        const size_t extent = (size_t)((int64_t)(n_frames - 1) * frame_stride + frame_extent);
+        if (ranges_overlap(out, extent * sizeof(float), image, extent * sizeof(float)) ||
+            ranges_overlap(out, extent * sizeof(float), mask, extent))
+            return fail(FSR_ERR_INVALID_ARG, "out must not overlap image or mask");
+    }
     const int S = params->block + 2 * params->border;
     if (S != kS || params->dft != FSR_DFT_FP32 || params->flags != 0)
         return fail(FSR_ERR_UNSUPPORTED, "the reuse variant runs at S = 32 with FSR_DFT_FP32 and no flags "
@@ -467,9 +487,29 @@ fsr_status fsr_reconstruct_reuse(fsr_context* ctx, const float* image, const uin
     PlainLaunch p = plain_launch(image, mask, out, height, width, stride, params, argmax_log);
     if ((st = context_tables(ctx, S, params->rho, &p.tab, cap == hipStreamCaptureStatusNone)) != FSR_OK)
         return st;
-    hipError_t e = launch_reuse(p, reuse_weight, (hipStream_t)stream);
+    hipError_t e = launch_reuse(p, reuse_weight, n_frames, n_frames > 1 ? frame_stride : 0,
+                                (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "launch of the reuse-variant kernels");
     return FSR_OK;
+}
+
+}  // namespace fsr
+
+extern "C" {
+
+fsr_status fsr_reconstruct_reuse(fsr_context* ctx, const float* image, const uint8_t* mask, float* out,
+                                 int32_t height, int32_t width, int64_t stride, const fsr_params* params,
+                                 float reuse_weight, uint16_t* argmax_log, void* stream) {
+    return reuse_call(ctx, image, mask, out, 1, height, width, stride, 0, params, reuse_weight, argmax_log,
+                      stream);
+}
+
+fsr_status fsr_reconstruct_reuse_frames(fsr_context* ctx, const float* image, const uint8_t* mask,
+                                        float* out, int32_t n_frames, int32_t height, int32_t width,
+                                        int64_t stride, int64_t frame_stride, const fsr_params* params,
+                                        float reuse_weight, uint16_t* argmax_log, void* stream) {
+    return reuse_call(ctx, image, mask, out, n_frames, height, width, stride, frame_stride, params,
+                      reuse_weight, argmax_log, stream);
 }
 
 }  // extern "C"

@@ -51,8 +51,10 @@ struct PlainLaunch {
 };
 
 hipError_t launch_plain(const PlainLaunch& p, hipStream_t stream);
-// The reuse variant at S = 32 (fsr_reuse.hip): one launch per wavefront step.
-hipError_t launch_reuse(const PlainLaunch& p, float delta, hipStream_t stream);
+// The reuse variant at S = 32 (fsr_reuse.hip): one launch per wavefront step
+// over n_frames frames of p.img's size, frame_stride elements apart.
+hipError_t launch_reuse(const PlainLaunch& p, float delta, int32_t n_frames, int64_t frame_stride,
+                        hipStream_t stream);
 int64_t reuse_steps(int32_t height, int32_t width, int32_t block, int32_t border);
 hipError_t launch_plain_sg(const PlainLaunch& p, hipStream_t stream);   // S = 8, 16, 24
 

@@ -102,6 +102,18 @@ def test_reuse_variant_validates_before_touching_the_device(lib):
         assert call(fake_ctx, img, msk, out, 8, 8, 8, p_other, 0.5) == binding.FSR_ERR_UNSUPPORTED
     assert "reuse" in lib.fsr_last_error_message().decode()
 
+    def frames(n, H, W, stride, fstride, o=out, delta=0.5, params=p):
+        return lib.fsr_reconstruct_reuse_frames(fake_ctx, img, msk, o, n, H, W, stride, fstride,
+                                                ctypes.byref(params), delta, None, None)
+
+    for n in (0, -1, 65536):
+        assert frames(n, 8, 8, 8, 64) == binding.FSR_ERR_INVALID_ARG
+    assert frames(2, 8, 8, 8, 63) == binding.FSR_ERR_INVALID_ARG      # frames overlap
+    # the last frame of out reaches into the image's range
+    assert frames(4, 8, 8, 8, 0x1000000, o=ctypes.c_void_p(0x10000 + 0x8000000)) == binding.FSR_ERR_INVALID_ARG
+    assert frames(2, 8, 8, 8, 64, delta=2.0) == binding.FSR_ERR_INVALID_ARG
+    assert frames(2, 8, 8, 8, 64, params=fsr.make_params(block=4, border=6)) == binding.FSR_ERR_UNSUPPORTED
+
 
 def test_missing_library_fails_loudly(tmp_path):
     with pytest.raises(fsr.FsrError):

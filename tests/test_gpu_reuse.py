@@ -253,3 +253,59 @@ def test_no_known_pixel_at_all(ctx):
     assert np.all(g == 0.0)
     assert np.array_equal(gl, ol)
     assert np.all(gl[0] == 0xFFFF) and np.all(gl[1:] == 0)
+
+
+# ---------------------------------------------------------------- several frames
+def frames_of(n, H, W, seed):
+    imgs = np.stack([synth.make_image(H, W, seed + 10 * f).astype(np.float32) for f in range(n)])
+    kinds = ("quarter", "uniform:0.3", "macroblock")
+    masks = np.stack([synth.make_mask(kinds[f % 3], H, W, seed + 10 * f + 1) for f in range(n)])
+    return imgs, masks
+
+
+@pytest.mark.parametrize("stride_pad,frame_pad", [(0, 0), (26, 40)])
+def test_frames_equal_one_frame_calls(ctx, stride_pad, frame_pad):
+    announce(f"reuse over 5 frames of 70x90 (row pad {stride_pad}, frame pad {frame_pad}) vs one-frame calls")
+    n, H, W = 5, 70, 90
+    imgs, masks = frames_of(n, H, W, 2900)
+    p = fsr.make_params(iterations=60)
+    stride = W + stride_pad
+    fstride = H * stride + frame_pad
+    bi = torch.zeros(n * fstride, dtype=torch.float32, device=DEV)
+    bm = torch.zeros(n * fstride, dtype=torch.uint8, device=DEV)
+    bo = torch.full((n * fstride,), -7.0, dtype=torch.float32, device=DEV)
+    view = lambda t: t.as_strided((n, H, W), (fstride, stride, 1))
+    view(bi).copy_(torch.from_numpy(imgs))
+    view(bm).copy_(torch.from_numpy(masks))
+    nb = fsr.fsr_num_blocks(H, W, 4)
+    lg = torch.full((n, nb, p.iterations), -1, dtype=torch.int16, device=DEV)
+    fsr.fsr_reconstruct_reuse_frames(ctx, view(bi), view(bm), view(bo), p, 0.5, lg)
+    torch.cuda.synchronize()
+    got = view(bo).cpu().numpy()
+    logs = lg.cpu().numpy().view(np.uint16)
+    for f in range(n):
+        ref, ref_log = run(ctx, imgs[f], masks[f], p, 0.5)
+        assert np.array_equal(got[f], ref), f"frame {f}"
+        assert np.array_equal(logs[f], ref_log), f"frame {f} log"
+    # nothing outside the frames' pixels is written
+    written = torch.zeros(n * fstride, dtype=torch.bool, device=DEV)
+    view(written).fill_(True)
+    assert torch.all(bo[~written] == -7.0)
+
+
+def test_frames_at_full_size(ctx):
+    announce("reuse over 3 frames of 1920x1080 vs one-frame calls")
+    w = synth.workload("fhd_quarter")
+    img, mask = w.inputs()
+    img32 = img.astype(np.float32)
+    imgs = np.stack([img32, img32[::-1].copy(), img32[:, ::-1].copy()])
+    masks = np.stack([mask, mask[:, ::-1].copy(), mask[::-1].copy()])
+    p = fsr.make_params()
+    ti, tm = torch.from_numpy(imgs).to(DEV), torch.from_numpy(masks).to(DEV)
+    out = torch.empty_like(ti)
+    fsr.fsr_reconstruct_reuse_frames(ctx, ti, tm, out, p, 0.5)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    for f in range(3):
+        ref, _ = run(ctx, imgs[f], masks[f], p, 0.5)
+        assert np.array_equal(got[f], ref), f"frame {f}"
