@@ -103,8 +103,9 @@ typedef struct fsr_context fsr_context;
 /* Library version as major*10000 + minor*100 + patch. */
 FSR_API int32_t fsr_version(void);
 
-/* Human-readable name of a status code (static storage). */
-FSR_API const char *fsr_status_string(fsr_status status);
+/* Human-readable name of a status code (static storage); any other value
+ * gives "FSR_ERR_UNKNOWN". */
+FSR_API const char *fsr_status_string(int32_t status);
 
 /* Message of the calling thread's last failure ("" if none; thread-local,
  * valid until the thread's next failing call). */

@@ -310,7 +310,7 @@ extern "C" {
 
 int32_t fsr_version(void) { return 100; }
 
-const char* fsr_status_string(fsr_status s) {
+const char* fsr_status_string(int32_t s) {
     switch (s) {
     case FSR_OK: return "FSR_OK";
     case FSR_ERR_INVALID_ARG: return "FSR_ERR_INVALID_ARG";
