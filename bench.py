@@ -85,6 +85,9 @@ def parse():
                     help="skip the 64-image batched comparison")
     ap.add_argument("--no-reuse", action="store_true",
                     help="skip the leg of the sequential variant that reuses reconstructed pixels")
+    ap.add_argument("--reuse-frames", default="4,16,64",
+                    help="frame counts (multiples of 4) timed by the reuse leg's several-frames part; "
+                         "'' for none")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the split-bf16 vs FP32-FFT comparison on the 3840x2160 frame")
     ap.add_argument("--serve-max-batch", type=int, default=2,
@@ -222,7 +225,7 @@ def bench_argmax_ablation(ctx, img32, mask, params, steps: int = 5):
     return res
 
 
-def bench_reuse(ctx, img32, mask, params, delta: float = 0.5, steps: int = 3):
+def bench_reuse(ctx, img32, mask, params, delta: float = 0.5, steps: int = 3, frame_counts=(4, 16, 64)):
     """The sequential variant that reuses reconstructed pixels (the original
     FSR the paper departs from) on the same frame: one launch per wavefront
     step, eagerly and as a replayed HIP graph, with its quality beside the
@@ -261,7 +264,7 @@ def bench_reuse(ctx, img32, mask, params, delta: float = 0.5, steps: int = 3):
     graph_ms = timed(g.replay)
     # frames of one size in one call: one launch per step takes every frame's blocks
     frames = {}
-    for n in (4, 16, 64):
+    for n in frame_counts:
         imgs = torch.stack([ti, ti.flip(0), ti.flip(1), ti.flip(0, 1)] * (n // 4)).contiguous()
         masks = torch.stack([tm, tm.flip(1), tm.flip(0), tm.flip(0, 1)] * (n // 4)).contiguous()
         outs = torch.empty_like(imgs)
@@ -703,7 +706,10 @@ def main():
     res["argmax_ablation"] = bench_argmax_ablation(ctx, img32, mask, params)
     res["multiresolution"] = bench_multiresolution(ctx)
     if not args.no_reuse:
-        res["reuse_variant"] = bench_reuse(ctx, img32, mask, params)
+        counts = tuple(int(x) for x in args.reuse_frames.split(",") if x.strip())
+        if any(n < 4 or n % 4 for n in counts):
+            sys.exit("--reuse-frames takes multiples of 4")
+        res["reuse_variant"] = bench_reuse(ctx, img32, mask, params, frame_counts=counts)
     if not args.no_batched:
         res["batched"] = bench_batched(ctx)
     if not args.no_precision:
