@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "fsr_runtime.h"
+#include "fsr_sched.h"
 
 namespace fsr {
 namespace {
@@ -33,50 +34,8 @@ double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
-
-// First-fit allocator over [0, size) with coalescing of neighbouring holes.
-class Arena {
-public:
-    void init(size_t size) {
-        free_.clear();
-        if (size) free_[0] = size;
-        used_ = 0;
-    }
-    bool alloc(size_t n, size_t* off) {
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second < n) continue;
-            *off = it->first;
-            const size_t rest = it->second - n, start = it->first + n;
-            free_.erase(it);
-            if (rest) free_[start] = rest;
-            used_ += n;
-            return true;
-        }
-        return false;
-    }
-    void release(size_t off, size_t n) {
-        used_ -= n;
-        auto next = free_.lower_bound(off);
-        if (next != free_.end() && off + n == next->first) {
-            n += next->second;
-            next = free_.erase(next);
-        }
-        if (next != free_.begin()) {
-            auto prev = std::prev(next);
-            if (prev->first + prev->second == off) {
-                prev->second += n;
-                return;
-            }
-        }
-        free_[off] = n;
-    }
-    size_t used() const { return used_; }
-
-private:
-    std::map<size_t, size_t> free_;
-    size_t used_ = 0;
-};
+using sched::align256;
+using sched::Arena;
 
 enum class State { Queued, Admitted, Launched, Done };
 
@@ -98,21 +57,11 @@ struct Launch {
     double work = 0.0;   // block-iterations of the batch
 };
 
-// A batch is started beside a running one only if it is at most this share
-// of the running batch's block-iterations: a small frame then finishes long
-// before the large one, while two large batches sharing the device would
-// both finish late.
-constexpr double kBesideShare = 0.25;
-
 double request_work(const fsr_request& r, const fsr_params& p) {
-    const double blocks = (double)((r.height + p.block - 1) / p.block) * (double)((r.width + p.block - 1) / p.block);
-    return blocks * (double)(r.iterations + 8);
+    return sched::request_work(r.height, r.width, r.iterations, p.block);
 }
 
-size_t request_bytes(const fsr_request& r) {
-    const size_t px = (size_t)r.height * (size_t)r.width;
-    return align256(4 * px) + align256(px) + align256(4 * px);
-}
+size_t request_bytes(const fsr_request& r) { return sched::request_bytes(r.height, r.width); }
 
 }  // namespace
 }  // namespace fsr
@@ -299,21 +248,13 @@ void launch_batches(fsr_server* s) {
             }
         if (si < 0) return;
         hipStream_t st = s->streams[si];
-        size_t n = std::min(s->admitted.size(), (size_t)s->cfg.max_batch);
-        if (!s->inflight.empty()) {
-            // another batch runs: take only a batch small beside it, if any
-            double running = 0.0;
-            for (const Launch& r : s->inflight) running = std::max(running, r.work);
-            double w = 0.0;
-            size_t k = 0;
-            for (auto it = s->admitted.begin(); it != s->admitted.end() && k < n; ++it, ++k) {
-                const double wk = request_work(s->reqs[*it].r, s->params);
-                if (w + wk > kBesideShare * running) break;
-                w += wk;
-            }
-            if (k == 0) return;   // wait for the running batch
-            n = k;
-        }
+        // beside a running batch only a small one (sched::batch_size)
+        double running = 0.0;
+        for (const Launch& r : s->inflight) running = std::max(running, r.work);
+        const size_t n = sched::batch_size(
+            s->admitted.size(), [&](size_t k) { return request_work(s->reqs[s->admitted[k]].r, s->params); },
+            (size_t)s->cfg.max_batch, running);
+        if (n == 0) return;   // wait for the running batch
         std::vector<fsr_image_desc> descs(n);
         Launch l;
         l.stream = si;
