@@ -95,6 +95,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=2400,
                     help="requests of the served comparison (0 skips it); the stated workload "
                          "is 10,000 (about 42 s per mode)")
+    ap.add_argument("--serve-log", default=None, metavar="PATH",
+                    help="append one JSON line per served request (both modes) to PATH")
     ap.add_argument("--realtime-seconds", type=float, default=5.0,
                     help="length of the four-stream real-time leg at S = 16 (0 skips it)")
     ap.add_argument("--sweep", action="store_true",
@@ -552,6 +554,14 @@ def bench_realtime_s16(ctx, seconds: float = 5.0, fps: float = 60.0, budget: int
         srv.close()
         lat = (a[:, 3] - a[:, 0]) * 1e3
         span = a[:, 3].max() - a[:, 0].min()
+        if log_path:
+            with open(log_path, "a") as fh:
+                for k, (row, req) in enumerate(zip(a, trace)):
+                    fh.write(json.dumps({"mode": name, "request": k, "height": req.item.height,
+                                         "width": req.item.width, "iterations": req.item.iterations,
+                                         "arrival_s": round(req.arrival_s, 6), "submit_s": row[0],
+                                         "admit_s": row[1], "launch_s": row[2], "done_s": row[3],
+                                         "latency_ms": round(float(lat[k]), 4)}) + "\n")
         per = {}
         for h, label in names.items():
             sel = a[:, 5] == h
@@ -571,12 +581,14 @@ def bench_realtime_s16(ctx, seconds: float = 5.0, fps: float = 60.0, budget: int
 
 
 def bench_served(ctx, n_requests: int, rate_hz: float = 240.0, budget: int = 4 << 30,
-                 max_batch: int = 2):
+                 max_batch: int = 2, log_path: str | None = None):
     """Poisson stream of frames (720p:1080p:2160p = 5:3:1, I = 100, quarter or
     10-50 % uniform-loss masks) replayed in real time against the
     continuous-batching server and against the FIFO one-frame-per-launch loop.
     Frame contents come from a pinned host pool of 3 frames per size; the
-    arrival times, sizes and order follow the seeded trace."""
+    arrival times, sizes and order follow the seeded trace.  With
+    ``log_path``, one JSON line per request and mode is appended there
+    (server clock times of submission, admission, launch and completion)."""
     import paper_2202_13926_amd as fsr
     import synth
 
@@ -603,6 +615,14 @@ def bench_served(ctx, n_requests: int, rate_hz: float = 240.0, budget: int = 4 <
         srv.close()
         lat = (a[:, 3] - a[:, 0]) * 1e3
         span = a[:, 3].max() - a[:, 0].min()
+        if log_path:
+            with open(log_path, "a") as fh:
+                for k, (row, req) in enumerate(zip(a, trace)):
+                    fh.write(json.dumps({"mode": name, "request": k, "height": req.item.height,
+                                         "width": req.item.width, "iterations": req.item.iterations,
+                                         "arrival_s": round(req.arrival_s, 6), "submit_s": row[0],
+                                         "admit_s": row[1], "launch_s": row[2], "done_s": row[3],
+                                         "latency_ms": round(float(lat[k]), 4)}) + "\n")
         out[name] = {"p50_ms": round(float(np.percentile(lat, 50)), 3),
                      "p99_ms": round(float(np.percentile(lat, 99)), 3),
                      "max_ms": round(float(lat.max()), 3),
@@ -715,7 +735,8 @@ def main():
     if not args.no_precision:
         res["precision"] = bench_precision(ctx)
     if args.serve_requests > 0:
-        res["served"] = bench_served(ctx, args.serve_requests, max_batch=args.serve_max_batch)
+        res["served"] = bench_served(ctx, args.serve_requests, max_batch=args.serve_max_batch,
+                                     log_path=args.serve_log)
     if args.realtime_seconds > 0:
         res["realtime_s16"] = bench_realtime_s16(ctx, args.realtime_seconds)
     if not args.no_cpu_baseline:
