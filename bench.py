@@ -95,6 +95,9 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=2400,
                     help="requests of the served comparison (0 skips it); the stated workload "
                          "is 10,000 (about 42 s per mode)")
+    ap.add_argument("--tuning-cache", default=None, metavar="PATH",
+                    help="load the batched path's autotune results from PATH if it exists, and "
+                         "write them back after the run")
     ap.add_argument("--serve-log", default=None, metavar="PATH",
                     help="append one JSON line per served request (both modes) to PATH")
     ap.add_argument("--realtime-seconds", type=float, default=5.0,
@@ -730,8 +733,14 @@ def main():
         if any(n < 4 or n % 4 for n in counts):
             sys.exit("--reuse-frames takes multiples of 4")
         res["reuse_variant"] = bench_reuse(ctx, img32, mask, params, frame_counts=counts)
+    if args.tuning_cache and os.path.exists(args.tuning_cache):
+        with open(args.tuning_cache) as fh:
+            fsr.fsr_batch_tuning_import(ctx, fh.read())
     if not args.no_batched:
         res["batched"] = bench_batched(ctx)
+    if args.tuning_cache:
+        with open(args.tuning_cache, "w") as fh:
+            fh.write(fsr.fsr_batch_tuning_export(ctx) + "\n")
     if not args.no_precision:
         res["precision"] = bench_precision(ctx)
     if args.serve_requests > 0:

@@ -264,6 +264,23 @@ FSR_API fsr_status fsr_batch_autotune(fsr_context *ctx, const fsr_image_desc *de
                                       void *workspace, size_t workspace_bytes, void *stream,
                                       fsr_batch_schedule *best);
 
+/*
+ * The context's autotune results as text, to be kept across processes:
+ * JSON of the form
+ *   {"format": "fsr-batch-tuning-1", "arch": "<gcnArchName>", "cus": <CUs>,
+ *    "entries": [[<size-class key>, waves_per_group, chunk, groups_per_cu], ...]}
+ * where the key packs log2 of the batch's work, the support, the dft mode
+ * and the largest iteration count.  Export writes a NUL-terminated string
+ * of *len bytes (NUL included) into buf when cap suffices (buf NULL: only
+ * *len is set; cap too small: FSR_ERR_INVALID_ARG with *len set).  Import
+ * reads exactly that form, checks every schedule as fsr_reconstruct_batched
+ * does and merges the entries into the context; text from another kind of
+ * device (arch or CU count) is FSR_ERR_UNSUPPORTED, malformed text
+ * FSR_ERR_INVALID_ARG, and nothing is merged then.
+ */
+FSR_API fsr_status fsr_batch_tuning_export(fsr_context *ctx, char *buf, size_t cap, size_t *len);
+FSR_API fsr_status fsr_batch_tuning_import(fsr_context *ctx, const char *json);
+
 /* A batch captured once into a HIP graph (queue reset + batched kernel) and
  * replayed many times: the images' device buffers are fixed at creation and
  * their contents are read at each replay.  Creation uploads the descriptors

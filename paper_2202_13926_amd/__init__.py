@@ -6,7 +6,8 @@ Python binding.  See :mod:`paper_2202_13926_amd.binding`.
 """
 from .binding import (  # noqa: F401
     FSR_DFT_FP32, FSR_DFT_SPLIT_BF16, FSR_FLAG_LDS_ARGMAX, BatchGraph, BatchItem, Context, FsrError, Workspace,
-    declared_functions, fsr_batch_autotune, fsr_batch_schedule, fsr_batched_workspace_size,
+    declared_functions, fsr_batch_autotune, fsr_batch_schedule, fsr_batch_tuning_export,
+    fsr_batch_tuning_import, fsr_batched_workspace_size,
     fsr_context_create, fsr_context_destroy, fsr_image_desc, fsr_num_blocks, fsr_params,
     fsr_params_default, fsr_params_validate, fsr_reconstruct, fsr_reconstruct_batched, fsr_reconstruct_reuse, fsr_reconstruct_reuse_frames, fsr_version,
     load_library, make_params, make_schedule, reconstruct, reconstruct_reuse,

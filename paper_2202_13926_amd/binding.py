@@ -146,6 +146,9 @@ def load_library(path: str | None = None):
                                                   ctypes.POINTER(fsr_batch_schedule), vp,
                                                   ctypes.c_size_t, ctypes.POINTER(vp)]),
         "fsr_batch_graph_launch": (ctypes.c_int, [vp, vp]),
+        "fsr_batch_tuning_export": (ctypes.c_int, [vp, ctypes.c_char_p, ctypes.c_size_t,
+                                                   ctypes.POINTER(ctypes.c_size_t)]),
+        "fsr_batch_tuning_import": (ctypes.c_int, [vp, ctypes.c_char_p]),
         "fsr_batch_graph_destroy": (ctypes.c_int, [vp]),
         "fsr_server_create": (ctypes.c_int, [vp, P, ctypes.POINTER(fsr_server_config),
                                              ctypes.POINTER(vp)]),
@@ -371,6 +374,21 @@ def reconstruct(image, mask, params: fsr_params | None = None, ctx: Context | No
 
 
 # ---------------------------------------------------------------- batches
+def fsr_batch_tuning_export(ctx: Context) -> str:
+    """The context's autotune results as JSON text (see include/fsr.h)."""
+    lib = load_library()
+    n = ctypes.c_size_t(0)
+    _check(lib.fsr_batch_tuning_export(ctx.handle, None, 0, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value)
+    _check(lib.fsr_batch_tuning_export(ctx.handle, buf, n.value, ctypes.byref(n)))
+    return buf.value.decode()
+
+
+def fsr_batch_tuning_import(ctx: Context, text: str) -> None:
+    """Merge autotune results exported on a device of the same kind."""
+    _check(load_library().fsr_batch_tuning_import(ctx.handle, text.encode()))
+
+
 class BatchItem:
     """One image of a batch: device tensors plus its iteration count."""
 

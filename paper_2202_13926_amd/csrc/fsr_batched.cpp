@@ -2,7 +2,11 @@
 // queue order, prefix sums), descriptor upload, schedules, the autotuner and
 // HIP-graph capture.
 #include <algorithm>
+#include <cctype>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <string>
 #include <numeric>
 #include <vector>
 
@@ -417,6 +421,161 @@ fsr_status fsr_batch_graph_destroy(fsr_batch_graph* graph) {
         if (graph->graph) (void)hipGraphDestroy(graph->graph);
     }
     delete graph;
+    return FSR_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- tuning cache
+namespace fsr {
+namespace {
+
+constexpr const char* kTuningFormat = "fsr-batch-tuning-1";
+
+fsr_status device_identity(fsr_context* ctx, std::string* arch, int* cus) {
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDeviceProperties(&prop, context_device(ctx));
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    *arch = prop.gcnArchName;
+    *cus = prop.multiProcessorCount;
+    return FSR_OK;
+}
+
+// A strict reader of the one JSON shape fsr_batch_tuning_export writes.
+struct Reader {
+    const char* p;
+    void ws() {
+        while (*p && std::isspace((unsigned char)*p)) ++p;
+    }
+    bool lit(char c) {
+        ws();
+        if (*p != c) return false;
+        ++p;
+        return true;
+    }
+    bool str(std::string* out) {
+        if (!lit('"')) return false;
+        out->clear();
+        while (*p && *p != '"') {
+            if (*p == '\\' || (unsigned char)*p < 0x20) return false;   // no escapes in this format
+            out->push_back(*p++);
+        }
+        if (*p != '"') return false;
+        ++p;
+        return true;
+    }
+    bool num(long long lo, long long hi, long long* out) {
+        ws();
+        if (!(*p == '-' || std::isdigit((unsigned char)*p))) return false;
+        char* end = nullptr;
+        const long long v = std::strtoll(p, &end, 10);
+        if (end == p || v < lo || v > hi) return false;
+        p = end;
+        *out = v;
+        return true;
+    }
+    bool unum(unsigned long long* out) {
+        ws();
+        if (!std::isdigit((unsigned char)*p)) return false;
+        char* end = nullptr;
+        *out = std::strtoull(p, &end, 10);
+        if (end == p) return false;
+        p = end;
+        return true;
+    }
+};
+
+}  // namespace
+}  // namespace fsr
+
+extern "C" {
+
+fsr_status fsr_batch_tuning_export(fsr_context* ctx, char* buf, size_t cap, size_t* len) {
+    if (!ctx || !len) return errorf(FSR_ERR_INVALID_ARG, "context and len must be non-NULL");
+    DeviceGuard g(context_device(ctx));
+    if (g.error() != hipSuccess) return hip_fail(g.error(), "hipSetDevice");
+    std::string arch;
+    int cus = 0;
+    fsr_status st = device_identity(ctx, &arch, &cus);
+    if (st != FSR_OK) return st;
+    std::string out = std::string("{\"format\": \"") + kTuningFormat + "\", \"arch\": \"" + arch +
+                      "\", \"cus\": " + std::to_string(cus) + ", \"entries\": [";
+    {
+        std::lock_guard<std::mutex> lock(context_mutex(ctx));
+        bool first = true;
+        for (const auto& kv : context_batch(ctx).tuned) {
+            char item[160];
+            std::snprintf(item, sizeof item, "%s[%llu, %d, %d, %d]", first ? "" : ", ",
+                          (unsigned long long)kv.first, kv.second.waves_per_group, kv.second.chunk,
+                          kv.second.groups_per_cu);
+            out += item;
+            first = false;
+        }
+    }
+    out += "]}";
+    *len = out.size() + 1;
+    if (!buf) return FSR_OK;
+    if (cap < *len) return errorf(FSR_ERR_INVALID_ARG, "buffer of %zu bytes is smaller than %zu", cap, *len);
+    std::memcpy(buf, out.c_str(), *len);
+    return FSR_OK;
+}
+
+fsr_status fsr_batch_tuning_import(fsr_context* ctx, const char* json) {
+    if (!ctx || !json) return errorf(FSR_ERR_INVALID_ARG, "context and json must be non-NULL");
+    // parse and check everything before the context is touched
+    Reader r{json};
+    std::string key, format, arch;
+    long long cus = -1;
+    std::map<uint64_t, fsr_batch_schedule> entries;
+    bool have_entries = false;
+    if (!r.lit('{')) return errorf(FSR_ERR_INVALID_ARG, "tuning text: expected '{'");
+    for (bool first = true;; first = false) {
+        if (!first && !r.lit(',')) break;
+        if (!r.str(&key) || !r.lit(':')) return errorf(FSR_ERR_INVALID_ARG, "tuning text: expected a key");
+        if (key == "format") {
+            if (!r.str(&format)) return errorf(FSR_ERR_INVALID_ARG, "tuning text: bad format");
+        } else if (key == "arch") {
+            if (!r.str(&arch)) return errorf(FSR_ERR_INVALID_ARG, "tuning text: bad arch");
+        } else if (key == "cus") {
+            if (!r.num(1, 1 << 20, &cus)) return errorf(FSR_ERR_INVALID_ARG, "tuning text: bad cus");
+        } else if (key == "entries") {
+            if (!r.lit('[')) return errorf(FSR_ERR_INVALID_ARG, "tuning text: entries must be a list");
+            have_entries = true;
+            if (!r.lit(']')) {
+                do {
+                    unsigned long long k = 0;
+                    long long w = 0, c = 0, gpc = 0;
+                    if (!r.lit('[') || !r.unum(&k) || !r.lit(',') || !r.num(0, 64, &w) || !r.lit(',') ||
+                        !r.num(0, 64, &c) || !r.lit(',') || !r.num(0, 1 << 20, &gpc) || !r.lit(']'))
+                        return errorf(FSR_ERR_INVALID_ARG, "tuning text: bad entry");
+                    const fsr_batch_schedule sch{(int32_t)w, (int32_t)c, (int32_t)gpc, 0};
+                    fsr_status st = check_schedule(&sch);
+                    if (st != FSR_OK) return st;
+                    entries[(uint64_t)k] = sch;
+                } while (r.lit(','));
+                if (!r.lit(']')) return errorf(FSR_ERR_INVALID_ARG, "tuning text: unterminated entries");
+            }
+        } else {
+            return errorf(FSR_ERR_INVALID_ARG, "tuning text: unknown key '%s'", key.c_str());
+        }
+    }
+    if (!r.lit('}')) return errorf(FSR_ERR_INVALID_ARG, "tuning text: expected '}'");
+    r.ws();
+    if (*r.p) return errorf(FSR_ERR_INVALID_ARG, "tuning text: trailing characters");
+    if (format != kTuningFormat || arch.empty() || cus < 0 || !have_entries)
+        return errorf(FSR_ERR_INVALID_ARG, "tuning text: format, arch, cus and entries are required");
+
+    DeviceGuard g(context_device(ctx));
+    if (g.error() != hipSuccess) return hip_fail(g.error(), "hipSetDevice");
+    std::string my_arch;
+    int my_cus = 0;
+    fsr_status st = device_identity(ctx, &my_arch, &my_cus);
+    if (st != FSR_OK) return st;
+    if (arch != my_arch || cus != my_cus)
+        return errorf(FSR_ERR_UNSUPPORTED, "tuning made on %s with %lld CUs; this device is %s with %d",
+                      arch.c_str(), cus, my_arch.c_str(), my_cus);
+    std::lock_guard<std::mutex> lock(context_mutex(ctx));
+    for (const auto& kv : entries) context_batch(ctx).tuned[kv.first] = kv.second;
     return FSR_OK;
 }
 

@@ -115,6 +115,24 @@ def test_reuse_variant_validates_before_touching_the_device(lib):
     assert frames(2, 8, 8, 8, 64, params=fsr.make_params(block=4, border=6)) == binding.FSR_ERR_UNSUPPORTED
 
 
+def test_tuning_import_rejects_malformed_text_before_touching_the_context(lib):
+    fake_ctx = ctypes.c_void_p(0x1000)        # never dereferenced: parsing fails first
+    good_head = '{"format": "fsr-batch-tuning-1", "arch": "gfx950", "cus": 256, "entries": '
+    bad = ["", "{}", "[", good_head + "[]", good_head + "[[1, 3, 0, 10]]}",     # waves 3
+           good_head + "[[1, 1, 65, 10]]}", good_head + "[[1, 1, 4, 33]]}",     # chunk, groups
+           good_head + "[[1, 1, 0]]}", good_head + "[]} x",
+           '{"format": "other", "arch": "gfx950", "cus": 256, "entries": []}',
+           '{"format": "fsr-batch-tuning-1", "arch": "gfx\\950", "cus": 256, "entries": []}',
+           '{"format": "fsr-batch-tuning-1", "cus": 256, "entries": []}',
+           '{"format": "fsr-batch-tuning-1", "arch": "gfx950", "cus": 256, "entries": [], "x": 1}']
+    for text in bad:
+        assert lib.fsr_batch_tuning_import(fake_ctx, text.encode()) == binding.FSR_ERR_INVALID_ARG, text
+    assert lib.fsr_batch_tuning_import(None, b"{}") == binding.FSR_ERR_INVALID_ARG
+    assert lib.fsr_batch_tuning_import(fake_ctx, None) == binding.FSR_ERR_INVALID_ARG
+    n = ctypes.c_size_t(0)
+    assert lib.fsr_batch_tuning_export(None, None, 0, ctypes.byref(n)) == binding.FSR_ERR_INVALID_ARG
+
+
 def test_missing_library_fails_loudly(tmp_path):
     with pytest.raises(fsr.FsrError):
         binding.load_library(str(tmp_path / "nope.so"))

@@ -5,6 +5,8 @@ each image's output and argmax log must be bitwise identical to a
 fsr_reconstruct call on it alone, whatever the schedule, the batch
 composition or the replay.
 """
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -195,3 +197,43 @@ def test_synthetic_uneven_batch_sampled(ctx):
         rep = parity_report(rt, mt, gt, ot, gl[ids], ol)
         print(f"[parity] synthetic batch image {k} {img.shape} I={it}: {rep}", flush=True)
         assert rep["known_bitwise"] and rep["frac_le_1"] >= 0.999 and rep["argmax_agree"] >= 0.99
+
+
+def test_tuning_results_travel_between_contexts(ctx):
+    announce("autotune results exported as JSON and imported into a fresh context")
+    import json
+
+    from paper_2202_13926_amd import binding
+    batch = uneven_batch(9)
+    refs = plain_reference(ctx, batch)
+    items = to_items(batch)
+    ws = fsr.Workspace(len(items), DEV)
+    best = fsr.fsr_batch_autotune(ctx, items, fsr.make_params(), ws)
+    text = fsr.fsr_batch_tuning_export(ctx)
+    doc = json.loads(text)
+    print("[tuning]", text[:200], flush=True)
+    assert doc["format"] == "fsr-batch-tuning-1" and doc["cus"] > 0 and doc["arch"]
+    assert [best.waves_per_group, best.chunk, best.groups_per_cu] in [e[1:] for e in doc["entries"]]
+    fresh = fsr.Context(0)
+    assert json.loads(fsr.fsr_batch_tuning_export(fresh))["entries"] == []
+    fsr.fsr_batch_tuning_import(fresh, text)
+    assert fsr.fsr_batch_tuning_export(fresh) == text
+    items = to_items(batch)
+    fsr.fsr_reconstruct_batched(fresh, items, fsr.make_params(), ws)   # the imported schedule
+    assert_same(results(items), refs)
+    # text from another kind of device is refused, and nothing is merged
+    other = dict(doc, arch=doc["arch"] + "-other", entries=[[1, 4, 2, 3]])
+    with pytest.raises(fsr.FsrError) as err:
+        fsr.fsr_batch_tuning_import(fresh, json.dumps(other))
+    assert err.value.status == binding.FSR_ERR_UNSUPPORTED
+    assert fsr.fsr_batch_tuning_export(fresh) == text
+    # a buffer one byte short is refused with the needed length
+    lib = binding.load_library()
+    n = ctypes.c_size_t(0)
+    assert lib.fsr_batch_tuning_export(fresh.handle, None, 0, ctypes.byref(n)) == binding.FSR_OK
+    short = ctypes.create_string_buffer(n.value - 1)
+    need = n.value
+    assert lib.fsr_batch_tuning_export(fresh.handle, short, n.value - 1, ctypes.byref(n)) == \
+        binding.FSR_ERR_INVALID_ARG
+    assert n.value == need
+    fresh.close()
