@@ -557,14 +557,6 @@ def bench_realtime_s16(ctx, seconds: float = 5.0, fps: float = 60.0, budget: int
         srv.close()
         lat = (a[:, 3] - a[:, 0]) * 1e3
         span = a[:, 3].max() - a[:, 0].min()
-        if log_path:
-            with open(log_path, "a") as fh:
-                for k, (row, req) in enumerate(zip(a, trace)):
-                    fh.write(json.dumps({"mode": name, "request": k, "height": req.item.height,
-                                         "width": req.item.width, "iterations": req.item.iterations,
-                                         "arrival_s": round(req.arrival_s, 6), "submit_s": row[0],
-                                         "admit_s": row[1], "launch_s": row[2], "done_s": row[3],
-                                         "latency_ms": round(float(lat[k]), 4)}) + "\n")
         per = {}
         for h, label in names.items():
             sel = a[:, 5] == h
