@@ -227,6 +227,29 @@ def bench_argmax_ablation(ctx, img32, mask, params, steps: int = 5):
     res = {tag: {"ms": round(ms, 4), "mpx_s": round(img32.size / ms / 1e3, 2)}
            for tag, ms in best.items()}
     res["speedup_register_over_lds"] = round(res["lds_argmax"]["ms"] / res["register_argmax"]["ms"], 3)
+    # the same comparison over the supports of Fig. 3 (B = 4, L = 2, 6, 10);
+    # at S = 8 the register path takes eight blocks per wavefront
+    by_support = {}
+    for L in (2, 6, 10):
+        times = {}
+        for tag, flags in (("register_ms", 0), ("lds_ms", fsr.FSR_FLAG_LDS_ARGMAX)):
+            p = fsr.make_params(block=4, border=L, iterations=params.iterations, rho=params.rho,
+                                gamma=params.gamma, flags=flags)
+            fsr.fsr_reconstruct(ctx, ti, tm, o, p, None, stream)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
+                fsr.fsr_reconstruct(ctx, ti, tm, o, p, None, stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times[tag] = round(e0.elapsed_time(e1) / steps, 4)
+        times["speedup_register_over_lds"] = round(times["lds_ms"] / times["register_ms"], 3)
+        by_support[f"S{4 + 2 * L}"] = times
+    by_support[f"S{params.block + 2 * params.border}"] = {
+        "register_ms": res["register_argmax"]["ms"], "lds_ms": res["lds_argmax"]["ms"],
+        "speedup_register_over_lds": res["speedup_register_over_lds"]}
+    res["by_support"] = by_support
     return res
 
 

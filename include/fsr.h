@@ -73,8 +73,8 @@ enum {
      * all S^2 (objective, bin) pairs instead of in registers across the
      * wavefront: the scheme Sec. IV compares the register-based argmax
      * against.  Same choices, hence bitwise the same output; slower.  For
-     * fsr_reconstruct with FSR_DFT_FP32 only (FSR_ERR_UNSUPPORTED
-     * elsewhere). */
+     * fsr_reconstruct with FSR_DFT_FP32 only, at every support (S = 8 then
+     * runs one block per wavefront); FSR_ERR_UNSUPPORTED elsewhere. */
     FSR_FLAG_LDS_ARGMAX = 1u
 };
 
@@ -86,7 +86,8 @@ enum {
  *   combination of FSR_FLAG_*.
  * This build runs S in {8, 16, 24, 32} with block <= 8 (FSR_ERR_UNSUPPORTED
  * otherwise), on the one-image, batched and served paths alike;
- * FSR_DFT_SPLIT_BF16 and FSR_FLAG_LDS_ARGMAX run S = 32 only.
+ * FSR_DFT_SPLIT_BF16 runs S = 32 only; FSR_FLAG_LDS_ARGMAX runs every
+ * support on the one-image path.
  */
 typedef struct fsr_params {
     int32_t block;       /* B: target block edge in pixels                  */

@@ -423,8 +423,8 @@ fsr_status fsr_reconstruct(fsr_context* ctx, const float* image, const uint8_t* 
     if ((params->flags & FSR_FLAG_LDS_ARGMAX) && params->dft != FSR_DFT_FP32)
         return fail(FSR_ERR_UNSUPPORTED, "the LDS argmax runs with FSR_DFT_FP32 only");
     const int S = params->block + 2 * params->border;
-    if (S != kS && (params->dft != FSR_DFT_FP32 || params->flags != 0))
-        return fail(FSR_ERR_UNSUPPORTED, "support %d runs with FSR_DFT_FP32 and no flags only", S);
+    if (S != kS && (params->dft != FSR_DFT_FP32 || (params->flags & ~FSR_FLAG_LDS_ARGMAX) != 0))
+        return fail(FSR_ERR_UNSUPPORTED, "support %d runs with FSR_DFT_FP32 only", S);
 
     DeviceGuard g(ctx->device);
     if (g.error() != hipSuccess) return hip_fail(g.error(), "hipSetDevice");

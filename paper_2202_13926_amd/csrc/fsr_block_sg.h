@@ -134,9 +134,23 @@ __device__ __forceinline__ void dft2_sg(const float (&v)[SgShape<S>::NS], float 
 // kPersistent: the caller loops over blocks; as in the S = 32 routine, the
 // lane index and table pointers are made opaque so that the compiler keeps
 // no per-block constant live across the caller's loop.
-template <int S, bool kPersistent = false>
+// (key, position) pairs of the shared-memory argmax: NS slots of 64 lanes,
+// padded to a power of two for the halving tree
+template <int S>
+constexpr int sg_argmax_pairs() {
+    int n = 64;
+    while (n < SgShape<S>::NS * 64) n *= 2;
+    return n;
+}
+
+// kArgmax: kArgmaxWave (keys reduced in registers and across the wavefront)
+// or kArgmaxLds, the shared-memory scheme Sec. IV compares against: every
+// (key, 64 slot + lane) pair goes to argmax_lds (sg_argmax_pairs<S>()
+// entries) and is halved in a tree; both choose the same bin.
+template <int S, bool kPersistent = false, int kArgmax = kArgmaxWave>
 __device__ __forceinline__ void reconstruct_block_sg(const BlockJob& jb, int B, int L, float gamma,
-                                                     const BlockTables& tab_in, float* lds) {
+                                                     const BlockTables& tab_in, float* lds,
+                                                     uint2* argmax_lds = nullptr) {
     constexpr int G = SgShape<S>::G, NS = SgShape<S>::NS, NL = SgShape<S>::NL;
     const int lane = kPersistent ? opaque((int)(threadIdx.x & 63)) : (int)(threadIdx.x & 63);
     BlockTables tab = tab_in;
@@ -248,17 +262,49 @@ __device__ __forceinline__ void reconstruct_block_sg(const BlockJob& jb, int B, 
         for (int it = 0; it < iters; ++it) {
             // objective key (Eq. 16), as in the S = 32 kernel: float32 bits
             // with the 4 low mantissa bits replaced by 15 - slot
-            uint32_t lmax = 0;
+            int slot, ln;
+            if constexpr (kArgmax == kArgmaxWave) {
+                uint32_t lmax = 0;
 #pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                const float e = fmaf(xr[s], xr[s], xi[s] * xi[s]);
-                const uint32_t key = (__float_as_uint(e * wf[s]) & 0xFFFFFFF0u) | (uint32_t)(15 - s);
-                lmax = umax(lmax, key);
+                for (int s = 0; s < NS; ++s) {
+                    const float e = fmaf(xr[s], xr[s], xi[s] * xi[s]);
+                    const uint32_t key = (__float_as_uint(e * wf[s]) & 0xFFFFFFF0u) | (uint32_t)(15 - s);
+                    lmax = umax(lmax, key);
+                }
+                if (!active) lmax = 0;   // real keys carry a slot code >= 4
+                const uint32_t mx = wave_max_u32(lmax);
+                ln = (int)__builtin_ctzll(ballot(lmax == mx));
+                slot = 15 - (int)(mx & 15u);
+            } else {
+                constexpr int kPairs = sg_argmax_pairs<S>();
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    const float e = fmaf(xr[s], xr[s], xi[s] * xi[s]);
+                    const uint32_t key = (__float_as_uint(e * wf[s]) & 0xFFFFFFF0u) | (uint32_t)(15 - s);
+                    argmax_lds[64 * s + lane] = make_uint2(active ? key : 0u, (uint32_t)(64 * s + lane));
+                }
+#pragma unroll
+                for (int e = 64 * NS; e < kPairs; e += 64) argmax_lds[e + lane] = make_uint2(0u, 0xFFFFFFFFu);
+                wave_sync();
+#pragma unroll
+                for (int half = kPairs / 2; half >= 64; half >>= 1) {
+#pragma unroll
+                    for (int j = 0; j < half / 64; ++j) {
+                        const int e = lane + 64 * j;
+                        argmax_lds[e] = better_pair(argmax_lds[e], argmax_lds[e + half]);
+                    }
+                    wave_sync();
+                }
+#pragma unroll
+                for (int half = 32; half >= 1; half >>= 1) {
+                    if (lane < half) argmax_lds[lane] = better_pair(argmax_lds[lane], argmax_lds[lane + half]);
+                    wave_sync();
+                }
+                const int pos = __builtin_amdgcn_readfirstlane((int)argmax_lds[0].y);
+                wave_sync();   // the next iteration overwrites the pairs
+                slot = pos >> 6;
+                ln = pos & 63;
             }
-            if (!active) lmax = 0;   // real keys carry a slot code >= 4
-            const uint32_t mx = wave_max_u32(lmax);
-            const int ln = (int)__builtin_ctzll(ballot(lmax == mx));
-            const int slot = 15 - (int)(mx & 15u);
             const int u = G * slot + ln / S, v = ln % S;
             const int idx = u * S + v;
             // the winner's slot is uniform: with few slots, branch on it

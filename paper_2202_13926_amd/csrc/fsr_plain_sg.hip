@@ -8,11 +8,13 @@
 
 namespace fsr {
 
-template <int S>
+template <int S, int kArgmax = kArgmaxWave>
 __global__ __launch_bounds__(64) void fsr_plain_sg(PlainLaunch p) {
-    __shared__ __align__(16) float lds[SgShape<S>::kLdsFloats];
+    constexpr int kExtra = kArgmax == kArgmaxLds ? 2 * sg_argmax_pairs<S>() : 0;
+    __shared__ __align__(16) float lds[SgShape<S>::kLdsFloats + kExtra];
     const int64_t blk = xcd_contiguous(blockIdx.x, p.n_blocks);
-    reconstruct_block_sg<S>(plain_job(p, blk), p.block, p.border, p.gamma, p.tab, lds);
+    reconstruct_block_sg<S, false, kArgmax>(plain_job(p, blk), p.block, p.border, p.gamma, p.tab, lds,
+                                            reinterpret_cast<uint2*>(lds + SgShape<S>::kLdsFloats));
 }
 
 template <int S, int T>
@@ -43,9 +45,20 @@ static hipError_t launch_multi(const PlainLaunch& p, hipStream_t stream) {
     return hipGetLastError();
 }
 
-// The host API admits FP32 DFTs and no flags at these supports.
+// The host API admits FP32 DFTs at these supports, and of the flags the
+// LDS argmax, which always runs one block per wavefront.
 hipError_t launch_plain_sg(const PlainLaunch& p, hipStream_t stream) {
     if (p.n_blocks <= 0) return hipSuccess;
+    if (p.lds_argmax) {
+        const dim3 grid((unsigned)p.n_blocks), block(64);
+        switch (p.support) {
+        case 8: hipLaunchKernelGGL((fsr_plain_sg<8, kArgmaxLds>), grid, block, 0, stream, p); break;
+        case 16: hipLaunchKernelGGL((fsr_plain_sg<16, kArgmaxLds>), grid, block, 0, stream, p); break;
+        case 24: hipLaunchKernelGGL((fsr_plain_sg<24, kArgmaxLds>), grid, block, 0, stream, p); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     const int bb = p.block * p.block;   // target pixels per block
     if (p.support == 8 && bb <= 8) return launch_multi<8, 1>(p, stream);
     if (p.support == 8 && bb <= 16) return launch_multi<8, 2>(p, stream);

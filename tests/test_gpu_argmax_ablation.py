@@ -70,3 +70,26 @@ def test_lds_argmax_edge_cases(ctx):
     a, la = run(ctx, img, mask, fsr.make_params(iterations=60))
     b, lb = run(ctx, img, mask, fsr.make_params(iterations=60, flags=fsr.FSR_FLAG_LDS_ARGMAX))
     assert np.array_equal(a, b) and np.array_equal(la, lb)
+
+
+@pytest.mark.parametrize("B,L", [(4, 2), (6, 1), (4, 6), (8, 4), (4, 10)])
+def test_lds_argmax_at_smaller_supports(ctx, B, L):
+    """Supports 8, 16, 24 (Fig. 3 spans S = 8 to 32): the LDS tree gives the
+    register path's result bitwise (at S = 8 with B <= 4 the register path
+    takes eight blocks per wavefront, the LDS variant one), and the oracle
+    pins it on a ragged frame."""
+    S = B + 2 * L
+    print(f"\n[gpu case] LDS argmax at S = {S} (B={B} L={L})", flush=True)
+    img = synth.make_image(90, 75, 3100 + S).astype(np.float32)
+    mask = synth.make_mask("quarter", 90, 75, 3200 + S)
+    reg = fsr.make_params(block=B, border=L, iterations=80)
+    lds = fsr.make_params(block=B, border=L, iterations=80, flags=fsr.FSR_FLAG_LDS_ARGMAX)
+    a, la = run(ctx, img, mask, reg)
+    b, lb = run(ctx, img, mask, lds)
+    assert np.array_equal(a, b) and np.array_equal(la, lb)
+    o, ol, _ = oracle.reconstruct(img.astype(np.float64), mask, 80, block_size=B, border=L, log=True,
+                                  decision=oracle.DECISION_KERNEL)
+    rep = parity_report(img, mask, b, o, lb, ol)
+    print(f"[parity] S={S}: {rep}", flush=True)
+    assert rep["known_bitwise"] and rep["frac_le_1"] >= 0.999 and rep["psnr_gap"] <= 0.05
+    assert rep["argmax_agree"] >= 0.99
