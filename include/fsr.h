@@ -161,7 +161,7 @@ FSR_API fsr_status fsr_reconstruct(fsr_context *ctx, const float *image, const u
  * reconstructed value and the weight reuse_weight * rho^dist (Eq. 5
  * scaled); known pixels keep Eq. 5's weight, and the other missing pixels
  * and those outside the image take no part.
- *   reuse_weight  in [0, 1] (the original method's publications use 0.5);
+ *   reuse_weight  in [0, 1] (the binding's default is 0.5);
  *                 0 reuses nothing and gives fsr_reconstruct's result
  *   other arguments as for fsr_reconstruct; `out` is also read: the
  *                 blocks read earlier blocks' reconstructions from it

@@ -45,9 +45,9 @@
  *     unknown target pixels are 0 and its log entries are 0xFFFF.
  *   - Unknown pixels take Re g; outputs are not clipped.
  *   - O9: "earlier" is raster order of the blocks (block row, then block
- *     column); delta is a parameter in [0, 1] (the original method's
- *     publications use 0.5); delta = 0 reuses nothing, so the variant then
- *     equals the block-independent method.
+ *     column); delta is a parameter in [0, 1] (the tests use 0.25 to 1);
+ *     delta = 0 reuses nothing, so the variant then equals the
+ *     block-independent method.
  *
  * Build: gcc -O2 -std=c11 -fPIC -shared -fopenmp -ffp-contract=off
  * (no fast-math: the symmetry arguments above rely on IEEE rounding).
