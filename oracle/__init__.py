@@ -48,25 +48,28 @@ def _load():
         lib.fsro_spatial_weight.argtypes = [c_int, c_double, u8p, dp]
         lib.fsro_freq_weight.argtypes = [c_int, dp]
         lib.fsro_dft2_real.argtypes = [c_int, dp, dp, dp]
-        lib.fsro_block.argtypes = [c_int, c_int, c_double, c_double, c_int, c_int, dp, u8p,
+        lib.fsro_block.argtypes = [c_int, c_int, c_double, c_double, c_int, dp, u8p,
                                    dp, dp, dp, dp, u16p, dp]
         lib.fsro_block.restype = c_int
         lib.fsro_model_pixel.argtypes = [c_int, dp, dp, c_int, c_int]
         lib.fsro_model_pixel.restype = c_double
         lib.fsro_reconstruct.argtypes = [dp, u8p, dp, c_int, c_int, c_long, c_int, c_int, c_int,
-                                         c_double, c_double, c_int, c_int, u16p, c_int]
+                                         c_double, c_double, c_int, u16p, c_int]
         lib.fsro_reconstruct.restype = c_long
         lib.fsro_reconstruct_blocks.argtypes = [dp, u8p, c_int, c_int, c_long, c_int, c_int,
-                                                c_int, c_double, c_double, c_int, c_int, i64p, c_long,
+                                                c_int, c_double, c_double, c_int, i64p, c_long,
                                                 dp, u16p, dp, c_int]
         lib.fsro_reconstruct_blocks.restype = c_long
-        lib.fsro_block_weighted.argtypes = [c_int, c_int, c_double, c_int, c_int, dp, dp,
+        lib.fsro_block_weighted.argtypes = [c_int, c_int, c_double, c_int, dp, dp,
                                             dp, dp, dp, dp, u16p, dp]
         lib.fsro_block_weighted.restype = c_int
         lib.fsro_reconstruct_reuse.argtypes = [dp, u8p, dp, c_int, c_int, c_long, c_int, c_int,
-                                               c_int, c_double, c_double, c_double, c_int, c_int,
-                                               u16p]
+                                               c_int, c_double, c_double, c_double, c_int, u16p]
         lib.fsro_reconstruct_reuse.restype = c_long
+        lib.fsro_reconstruct_reuse_given.argtypes = [dp, u8p, dp, dp, c_int, c_int, c_long, c_int,
+                                                     c_int, c_int, c_double, c_double, c_double,
+                                                     c_int, u16p, c_int]
+        lib.fsro_reconstruct_reuse_given.restype = c_long
         lib.fsro_max_threads.restype = c_int
         _lib = lib
     return _lib
@@ -123,13 +126,8 @@ def dft2_real_parts(x: np.ndarray):
     return Xr, Xi
 
 
-# Precision in which the argmax decision is taken (see fsr_oracle.c).
-DECISION_FP64 = 0
-DECISION_KERNEL = 1
-
-
 def block(ft: np.ndarray, known: np.ndarray, iters: int, rho: float, gamma: float,
-          tie_larger: bool = False, decision: int = DECISION_FP64):
+          tie_larger: bool = False):
     """Run O2-O6 on one S x S support block.
 
     Returns a dict with the final model ``G`` and residual ``R`` (complex
@@ -142,7 +140,7 @@ def block(ft: np.ndarray, known: np.ndarray, iters: int, rho: float, gamma: floa
     idx = np.empty(max(iters, 1), np.uint16)
     p = np.empty(2 * max(iters, 1))
     D = ctypes.c_double
-    empty = _load().fsro_block(S, iters, rho, gamma, int(tie_larger), int(decision), _p(ft, D),
+    empty = _load().fsro_block(S, iters, rho, gamma, int(tie_larger), _p(ft, D),
                                _p(k, ctypes.c_uint8), _p(Gr, D), _p(Gi, D), _p(Rr, D),
                                _p(Ri, D), _p(idx, ctypes.c_uint16), _p(p, D))
     return {"G": Gr + 1j * Gi, "R": Rr + 1j * Ri, "Gr": Gr, "Gi": Gi, "Rr": Rr, "Ri": Ri,
@@ -151,7 +149,7 @@ def block(ft: np.ndarray, known: np.ndarray, iters: int, rho: float, gamma: floa
 
 
 def block_weighted(ft: np.ndarray, w: np.ndarray, iters: int, gamma: float,
-                   tie_larger: bool = False, decision: int = DECISION_FP64):
+                   tie_larger: bool = False):
     """Run O3-O6 on one support block with a given spatial weight ``w``
     (S x S).  Returns the same dict as :func:`block`."""
     ft = _f64(ft)
@@ -161,9 +159,9 @@ def block_weighted(ft: np.ndarray, w: np.ndarray, iters: int, gamma: float,
     idx = np.empty(max(iters, 1), np.uint16)
     p = np.empty(2 * max(iters, 1))
     D = ctypes.c_double
-    empty = _load().fsro_block_weighted(S, iters, gamma, int(tie_larger), int(decision),
-                                        _p(ft, D), _p(w, D), _p(Gr, D), _p(Gi, D), _p(Rr, D),
-                                        _p(Ri, D), _p(idx, ctypes.c_uint16), _p(p, D))
+    empty = _load().fsro_block_weighted(S, iters, gamma, int(tie_larger), _p(ft, D), _p(w, D),
+                                        _p(Gr, D), _p(Gi, D), _p(Rr, D), _p(Ri, D),
+                                        _p(idx, ctypes.c_uint16), _p(p, D))
     return {"G": Gr + 1j * Gi, "R": Rr + 1j * Ri, "Gr": Gr, "Gi": Gi, "Rr": Rr, "Ri": Ri,
             "idx": idx[:iters].copy(), "p": (p[0::2] + 1j * p[1::2])[:iters],
             "empty": bool(empty)}
@@ -177,8 +175,7 @@ def model_pixel(G: np.ndarray, m: int, n: int) -> float:
 
 def reconstruct(image: np.ndarray, mask: np.ndarray, iters: int, block_size: int = 4,
                 border: int = 14, rho: float = 0.7, gamma: float = 0.5,
-                tie_larger: bool = False, log: bool = False, threads: int = 0,
-                decision: int = DECISION_FP64):
+                tie_larger: bool = False, log: bool = False, threads: int = 0):
     """Whole-image FP64 reconstruction.  Returns ``(out, log_idx, n_empty)``;
     ``log_idx`` is an (N, I) uint16 array when ``log`` is set, else None."""
     img = _f64(image)
@@ -190,8 +187,8 @@ def reconstruct(image: np.ndarray, mask: np.ndarray, iters: int, block_size: int
     lg = np.empty((N, max(iters, 1)), np.uint16) if log else None
     n_empty = _load().fsro_reconstruct(_p(img, ctypes.c_double), _p(m, ctypes.c_uint8),
                                        _p(out, ctypes.c_double), H, W, W, B, border, iters,
-                                       rho, gamma, int(tie_larger), int(decision),
-                                       _p(lg, ctypes.c_uint16), threads)
+                                       rho, gamma, int(tie_larger), _p(lg, ctypes.c_uint16),
+                                       threads)
     if lg is not None:
         lg = lg[:, :iters]
     return out, lg, int(n_empty)
@@ -200,7 +197,7 @@ def reconstruct(image: np.ndarray, mask: np.ndarray, iters: int, block_size: int
 def reconstruct_blocks(image: np.ndarray, mask: np.ndarray, block_ids, iters: int,
                        block_size: int = 4, border: int = 14, rho: float = 0.7,
                        gamma: float = 0.5, tie_larger: bool = False, log: bool = False,
-                       log_p: bool = False, threads: int = 0, decision: int = DECISION_FP64):
+                       log_p: bool = False, threads: int = 0):
     """FP64 reconstruction of selected blocks.  Returns ``(targets, log_idx,
     p, n_empty)``; ``targets`` is (n, B, B) with NaN outside the image."""
     img = _f64(image)
@@ -214,7 +211,7 @@ def reconstruct_blocks(image: np.ndarray, mask: np.ndarray, block_ids, iters: in
     lp = np.empty((n, max(iters, 1), 2)) if log_p else None
     n_empty = _load().fsro_reconstruct_blocks(
         _p(img, ctypes.c_double), _p(m, ctypes.c_uint8), H, W, W, B, border, iters, rho, gamma,
-        int(tie_larger), int(decision), _p(ids, ctypes.c_int64), n, _p(tg, ctypes.c_double),
+        int(tie_larger), _p(ids, ctypes.c_int64), n, _p(tg, ctypes.c_double),
         _p(lg, ctypes.c_uint16), _p(lp, ctypes.c_double), threads)
     if lg is not None:
         lg = lg[:, :iters]
@@ -224,8 +221,7 @@ def reconstruct_blocks(image: np.ndarray, mask: np.ndarray, block_ids, iters: in
 
 def reconstruct_reuse(image: np.ndarray, mask: np.ndarray, iters: int, delta: float = 0.5,
                       block_size: int = 4, border: int = 14, rho: float = 0.7,
-                      gamma: float = 0.5, tie_larger: bool = False, log: bool = False,
-                      decision: int = DECISION_FP64):
+                      gamma: float = 0.5, tie_larger: bool = False, log: bool = False):
     """Sequential FP64 reconstruction that reuses reconstructed pixels (O9):
     blocks in raster order, missing pixels of earlier blocks' targets taking
     part with their reconstruction and the weight ``delta`` rho^dist.
@@ -239,8 +235,35 @@ def reconstruct_reuse(image: np.ndarray, mask: np.ndarray, iters: int, delta: fl
     lg = np.empty((N, max(iters, 1)), np.uint16) if log else None
     n_empty = _load().fsro_reconstruct_reuse(_p(img, ctypes.c_double), _p(m, ctypes.c_uint8),
                                              _p(out, ctypes.c_double), H, W, W, B, border, iters,
-                                             rho, gamma, delta, int(tie_larger), int(decision),
+                                             rho, gamma, delta, int(tie_larger),
                                              _p(lg, ctypes.c_uint16))
+    if lg is not None:
+        lg = lg[:, :iters]
+    return out, lg, int(n_empty)
+
+
+def reconstruct_reuse_given(image: np.ndarray, mask: np.ndarray, reused: np.ndarray, iters: int,
+                            delta: float = 0.5, block_size: int = 4, border: int = 14,
+                            rho: float = 0.7, gamma: float = 0.5, tie_larger: bool = False,
+                            log: bool = False, threads: int = 0):
+    """Every block of the sequential variant on its own, its reused pixels
+    taken from the frame ``reused`` (same shape as ``image``) rather than
+    from the oracle's own earlier blocks.  Returns ``(out, log_idx, n_empty)``
+    like :func:`reconstruct_reuse`; fed that function's own output it
+    returns the same output and log."""
+    img = _f64(image)
+    m = _u8(mask)
+    src = _f64(reused)
+    H, W = img.shape
+    assert src.shape == img.shape
+    B = block_size
+    N = (-(-H // B)) * (-(-W // B))
+    out = np.zeros_like(img)
+    lg = np.empty((N, max(iters, 1)), np.uint16) if log else None
+    n_empty = _load().fsro_reconstruct_reuse_given(
+        _p(img, ctypes.c_double), _p(m, ctypes.c_uint8), _p(src, ctypes.c_double),
+        _p(out, ctypes.c_double), H, W, W, B, border, iters, rho, gamma, delta, int(tie_larger),
+        _p(lg, ctypes.c_uint16), threads)
     if lg is not None:
         lg = lg[:, :iters]
     return out, lg, int(n_empty)

@@ -25,20 +25,18 @@
  *       original FSR that the paper departs from (Sec. II): blocks in
  *       raster order, and a missing support pixel in the target of an
  *       earlier block counts as known with its reconstructed value and the
- *       weight delta rho^dist (fsro_reconstruct_reuse)
+ *       weight delta rho^dist (fsro_reconstruct_reuse); and each of its
+ *       blocks on its own, given the frame the reused pixels come from
+ *       (fsro_reconstruct_reuse_given)
  *
  * Readings of points the paper leaves open (each is listed with its reason
  * in the design notes):
  *   - DFT convention: forward unnormalised with e^{-j2pi(km+ln)/S}, k pairs
  *     with the row index m.  This is the convention under which Eq. 10 is
  *     the weighted least-squares coefficient and Eq. 12 holds exactly.
- *   - Argmax ties: larger objective wins; equal objectives go to the smaller
- *     linear index k*S + l (tie_larger = 1 flips this, for tests only).
- *   - Precision of the argmax decision (`decision`): 0 compares the FP64
- *     objectives; 1 takes the decision at the GPU kernel's precision: each
- *     objective is rounded to float32 and its 4 lowest mantissa bits are
- *     cleared before comparing (ties again to the smaller index).  Only the
- *     comparison changes; every other step stays in FP64.
+ *   - Argmax (Eq. 8): the FP64 objectives are compared as they are; the
+ *     larger wins, equal objectives go to the smaller linear index k*S + l
+ *     (tie_larger = 1 flips this, for tests only).
  *   - The twiddle table is exactly conjugate-symmetric so that the spectra of
  *     real inputs are bitwise Hermitian.
  *   - A support with no known pixel (W[0,0] == 0) runs no iteration; its
@@ -62,20 +60,6 @@
 #endif
 
 #define FSRO_API __attribute__((visibility("default")))
-
-/* Objective used for comparisons: the value itself (decision 0), or its
- * float32 rounding with the 4 lowest mantissa bits cleared (decision 1),
- * returned as a double so both compare with the same operators. */
-static double decision_value(double obj, int decision)
-{
-    if (decision == 0) return obj;
-    float f = (float)obj;
-    uint32_t u;
-    memcpy(&u, &f, sizeof u);
-    u &= ~(uint32_t)0xF;
-    memcpy(&f, &u, sizeof f);
-    return (double)f;
-}
 
 /* t[q] = exp(-j 2 pi q / S), q in [0, S), with t[S-q] = conj(t[q]) exactly
  * and the quarter points set exactly when S is a multiple of 4. */
@@ -175,19 +159,19 @@ FSRO_API void fsro_dft2_real(int S, const double *x, double *Xr, double *Xi)
  *   log_p   2I entries: projection coefficient p (re, im) per iteration
  * Returns 1 when the support holds no known pixel (no iteration ran), else 0.
  */
-FSRO_API int fsro_block_weighted(int S, int iters, double gamma, int tie_larger, int decision,
+FSRO_API int fsro_block_weighted(int S, int iters, double gamma, int tie_larger,
                                  const double *ft, const double *w,
                                  double *Gr_out, double *Gi_out, double *Rr_out, double *Ri_out,
                                  uint16_t *log_idx, double *log_p);
 
 FSRO_API int fsro_block(int S, int iters, double rho, double gamma, int tie_larger,
-                        int decision, const double *ft, const uint8_t *known,
+                        const double *ft, const uint8_t *known,
                         double *Gr_out, double *Gi_out, double *Rr_out, double *Ri_out,
                         uint16_t *log_idx, double *log_p)
 {
     double *w = malloc(sizeof(double) * S * S);
     fsro_spatial_weight(S, rho, known, w);                /* O2 */
-    int empty = fsro_block_weighted(S, iters, gamma, tie_larger, decision, ft, w, Gr_out, Gi_out,
+    int empty = fsro_block_weighted(S, iters, gamma, tie_larger, ft, w, Gr_out, Gi_out,
                                     Rr_out, Ri_out, log_idx, log_p);
     free(w);
     return empty;
@@ -199,7 +183,7 @@ FSRO_API int fsro_block(int S, int iters, double rho, double gamma, int tie_larg
  * the reuse variant (O9) one with a third class of pixels.  Outputs as for
  * fsro_block; returns 1 when W[0,0] is not positive (no iteration ran).
  */
-FSRO_API int fsro_block_weighted(int S, int iters, double gamma, int tie_larger, int decision,
+FSRO_API int fsro_block_weighted(int S, int iters, double gamma, int tie_larger,
                                  const double *ft, const double *w,
                                  double *Gr_out, double *Gi_out, double *Rr_out, double *Ri_out,
                                  uint16_t *log_idx, double *log_p)
@@ -228,7 +212,7 @@ FSRO_API int fsro_block_weighted(int S, int iters, double gamma, int tie_larger,
         int best = 0;
         double best_obj = -1.0;
         for (int b = 0; b < n2; ++b) {
-            double obj = decision_value(wf[b] * (Rr[b] * Rr[b] + Ri[b] * Ri[b]), decision);
+            double obj = wf[b] * (Rr[b] * Rr[b] + Ri[b] * Ri[b]);
             if (tie_larger ? (obj >= best_obj) : (obj > best_obj)) {
                 best_obj = obj;
                 best = b;
@@ -295,7 +279,7 @@ static void gather_support(const double *img, const uint8_t *mask, int H, int W,
  * (row-major B x B; entries of out-of-image pixels are left untouched). */
 static int reconstruct_one(const double *img, const uint8_t *mask, int H, int W, long stride,
                            int B, int L, int iters, double rho, double gamma, int tie_larger,
-                           int decision, long block_id, double *out_target, uint16_t *log_idx, double *log_p)
+                           long block_id, double *out_target, uint16_t *log_idx, double *log_p)
 {
     const int S = B + 2 * L, n2 = S * S;
     const int nbx = (W + B - 1) / B;
@@ -304,7 +288,7 @@ static int reconstruct_one(const double *img, const uint8_t *mask, int H, int W,
     uint8_t *known = malloc(n2);
     double *Gr = malloc(sizeof(double) * n2), *Gi = malloc(sizeof(double) * n2);
     gather_support(img, mask, H, W, stride, B, L, by, bx, ft, known);
-    int empty = fsro_block(S, iters, rho, gamma, tie_larger, decision, ft, known, Gr, Gi,
+    int empty = fsro_block(S, iters, rho, gamma, tie_larger, ft, known, Gr, Gi,
                            NULL, NULL, log_idx, log_p);
     for (int i = 0; i < B; ++i)
         for (int j = 0; j < B; ++j) {
@@ -328,7 +312,7 @@ static int reconstruct_one(const double *img, const uint8_t *mask, int H, int W,
  */
 FSRO_API long fsro_reconstruct(const double *img, const uint8_t *mask, double *out,
                                int H, int W, long stride, int B, int L, int iters,
-                               double rho, double gamma, int tie_larger, int decision,
+                               double rho, double gamma, int tie_larger,
                                uint16_t *log_idx, int threads)
 {
     const int nby = (H + B - 1) / B, nbx = (W + B - 1) / B;
@@ -342,7 +326,7 @@ FSRO_API long fsro_reconstruct(const double *img, const uint8_t *mask, double *o
         double tgt[32 * 32];
         double *t = (B * B <= 32 * 32) ? tgt : malloc(sizeof(double) * B * B);
         empty += reconstruct_one(img, mask, H, W, stride, B, L, iters, rho, gamma, tie_larger,
-                                 decision, b, t, log_idx ? log_idx + b * (long)iters : NULL,
+                                 b, t, log_idx ? log_idx + b * (long)iters : NULL,
                                  NULL);
         const int by = (int)(b / nbx), bx = (int)(b % nbx);
         for (int i = 0; i < B; ++i)
@@ -366,7 +350,7 @@ FSRO_API long fsro_reconstruct(const double *img, const uint8_t *mask, double *o
  */
 FSRO_API long fsro_reconstruct_blocks(const double *img, const uint8_t *mask,
                                       int H, int W, long stride, int B, int L, int iters,
-                                      double rho, double gamma, int tie_larger, int decision,
+                                      double rho, double gamma, int tie_larger,
                                       const int64_t *block_ids, long n, double *out_targets,
                                       uint16_t *log_idx, double *log_p, int threads)
 {
@@ -379,7 +363,7 @@ FSRO_API long fsro_reconstruct_blocks(const double *img, const uint8_t *mask,
         double *t = out_targets + i * (long)B * B;
         for (int q = 0; q < B * B; ++q) t[q] = NAN;
         empty += reconstruct_one(img, mask, H, W, stride, B, L, iters, rho, gamma, tie_larger,
-                                 decision, (long)block_ids[i], t,
+                                 (long)block_ids[i], t,
                                  log_idx ? log_idx + i * (long)iters : NULL,
                                  log_p ? log_p + 2 * i * (long)iters : NULL);
     }
@@ -387,61 +371,114 @@ FSRO_API long fsro_reconstruct_blocks(const double *img, const uint8_t *mask,
 }
 
 /*
- * O9: the sequential variant.  Blocks run one after another in raster order
- * (block row, then block column).  In the support of block (by, bx) a pixel
- * takes part
+ * One block of the sequential variant (O9).  In the support of block
+ * (by, bx) a pixel takes part
  *   - as known, weight rho^dist, value from img, where mask marks it;
- *   - as reused, weight delta rho^dist, value from out, where it is missing
- *     but lies in the target of an earlier block, which has already written
- *     its reconstruction to out (only when delta > 0);
+ *   - as reused, weight delta rho^dist, value from src, where it is missing
+ *     but lies in the target of an earlier block in raster order (only when
+ *     delta > 0);
  *   - not at all otherwise (missing pixels of this or later blocks, pixels
  *     outside the image).
- * Each block then runs O3-O8 as in the block-independent method and writes
- * its target to out.  Arguments as for fsro_reconstruct plus delta; out is
- * read as well as written and must not alias img.  Returns the number of
- * blocks whose support held no pixel with positive weight.
+ * The block then runs O3-O8 as in the block-independent method and writes
+ * its in-image target pixels to dst.  rp is rho^dist on the whole support.
+ * Returns 1 when no support pixel has a positive weight.
+ */
+static int reuse_block(const double *img, const uint8_t *mask, const double *src, double *dst,
+                       int H, int W, long stride, int B, int L, int iters, const double *rp,
+                       double gamma, double delta, int tie_larger, int by, int bx,
+                       uint16_t *log_idx)
+{
+    const int S = B + 2 * L, n2 = S * S;
+    double *ft = malloc(sizeof(double) * n2), *w = malloc(sizeof(double) * n2);
+    double *Gr = malloc(sizeof(double) * n2), *Gi = malloc(sizeof(double) * n2);
+    uint8_t *known = malloc(n2);
+    const int y0 = by * B - L, x0 = bx * B - L;
+    for (int m = 0; m < S; ++m)
+        for (int n = 0; n < S; ++n) {
+            const int y = y0 + m, x = x0 + n, i = m * S + n;
+            const int in = (y >= 0 && y < H && x >= 0 && x < W);
+            const int k = in && mask[(long)y * stride + x] != 0;
+            const int earlier = y < by * B || (y < (by + 1) * B && x < bx * B);
+            const int reused = in && !k && earlier && delta > 0.0;
+            known[i] = (uint8_t)k;
+            ft[i] = k ? img[(long)y * stride + x] : reused ? src[(long)y * stride + x] : 0.0;
+            w[i] = k ? rp[i] : reused ? delta * rp[i] : 0.0;
+        }
+    const int empty = fsro_block_weighted(S, iters, gamma, tie_larger, ft, w, Gr, Gi, NULL, NULL,
+                                          log_idx, NULL);
+    for (int i = 0; i < B; ++i)                           /* O8 on the target */
+        for (int j = 0; j < B; ++j) {
+            const int y = by * B + i, x = bx * B + j, m = L + i, n = L + j;
+            if (y >= H || x >= W) continue;
+            dst[(long)y * stride + x] = known[m * S + n]
+                ? ft[m * S + n] : fsro_model_pixel(S, Gr, Gi, m, n);
+        }
+    free(ft); free(w); free(Gr); free(Gi); free(known);
+    return empty;
+}
+
+/*
+ * O9: the sequential variant.  Blocks run one after another in raster order
+ * (block row, then block column), each reading its reused pixels from out,
+ * where the earlier blocks have already written their reconstructions.
+ * Arguments as for fsro_reconstruct plus delta; out is read as well as
+ * written and must not alias img.  Returns the number of blocks whose
+ * support held no pixel with positive weight.
  */
 FSRO_API long fsro_reconstruct_reuse(const double *img, const uint8_t *mask, double *out,
                                      int H, int W, long stride, int B, int L, int iters,
                                      double rho, double gamma, double delta, int tie_larger,
-                                     int decision, uint16_t *log_idx)
+                                     uint16_t *log_idx)
 {
     const int S = B + 2 * L, n2 = S * S;
     const int nby = (H + B - 1) / B, nbx = (W + B - 1) / B;
-    double *ft = malloc(sizeof(double) * n2), *w = malloc(sizeof(double) * n2);
     double *rp = malloc(sizeof(double) * n2);
-    double *Gr = malloc(sizeof(double) * n2), *Gi = malloc(sizeof(double) * n2);
-    uint8_t *all = malloc(n2), *known = malloc(n2);
+    uint8_t *all = malloc(n2);
     memset(all, 1, n2);
     fsro_spatial_weight(S, rho, all, rp);                 /* rho^dist everywhere */
     long empty = 0;
     for (int by = 0; by < nby; ++by)
         for (int bx = 0; bx < nbx; ++bx) {
             const long b = (long)by * nbx + bx;
-            const int y0 = by * B - L, x0 = bx * B - L;
-            for (int m = 0; m < S; ++m)
-                for (int n = 0; n < S; ++n) {
-                    const int y = y0 + m, x = x0 + n, i = m * S + n;
-                    const int in = (y >= 0 && y < H && x >= 0 && x < W);
-                    const int k = in && mask[(long)y * stride + x] != 0;
-                    const int earlier = y < by * B || (y < (by + 1) * B && x < bx * B);
-                    const int reused = in && !k && earlier && delta > 0.0;
-                    known[i] = (uint8_t)k;
-                    ft[i] = k ? img[(long)y * stride + x] : reused ? out[(long)y * stride + x] : 0.0;
-                    w[i] = k ? rp[i] : reused ? delta * rp[i] : 0.0;
-                }
-            empty += fsro_block_weighted(S, iters, gamma, tie_larger, decision, ft, w, Gr, Gi,
-                                         NULL, NULL, log_idx ? log_idx + b * (long)iters : NULL,
-                                         NULL);
-            for (int i = 0; i < B; ++i)                   /* O8 on the target */
-                for (int j = 0; j < B; ++j) {
-                    const int y = by * B + i, x = bx * B + j, m = L + i, n = L + j;
-                    if (y >= H || x >= W) continue;
-                    out[(long)y * stride + x] = known[m * S + n]
-                        ? ft[m * S + n] : fsro_model_pixel(S, Gr, Gi, m, n);
-                }
+            empty += reuse_block(img, mask, out, out, H, W, stride, B, L, iters, rp, gamma, delta,
+                                 tie_larger, by, bx, log_idx ? log_idx + b * (long)iters : NULL);
         }
-    free(ft); free(w); free(rp); free(Gr); free(Gi); free(all); free(known);
+    free(rp); free(all);
+    return empty;
+}
+
+/*
+ * Every block of the sequential variant (O9) taken on its own: the reused
+ * pixels of each support take their values from the frame `reused` (for
+ * example another implementation's output) instead of from this function's
+ * own earlier blocks.  Blocks are then independent and run in parallel.
+ * Given O9's own output as `reused`, each block sees exactly the inputs it
+ * saw inside O9, so `out` and the log equal O9's.  `out` must alias neither
+ * img nor reused; every in-image pixel of it is written.
+ */
+FSRO_API long fsro_reconstruct_reuse_given(const double *img, const uint8_t *mask,
+                                           const double *reused, double *out, int H, int W,
+                                           long stride, int B, int L, int iters, double rho,
+                                           double gamma, double delta, int tie_larger,
+                                           uint16_t *log_idx, int threads)
+{
+    const int S = B + 2 * L, n2 = S * S;
+    const int nby = (H + B - 1) / B, nbx = (W + B - 1) / B;
+    const long N = (long)nby * nbx;
+    double *rp = malloc(sizeof(double) * n2);
+    uint8_t *all = malloc(n2);
+    memset(all, 1, n2);
+    fsro_spatial_weight(S, rho, all, rp);
+    long empty = 0;
+#ifdef _OPENMP
+    if (threads <= 0) threads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 4) num_threads(threads) reduction(+ : empty)
+#endif
+    for (long b = 0; b < N; ++b)
+        empty += reuse_block(img, mask, reused, out, H, W, stride, B, L, iters, rp, gamma, delta,
+                             tie_larger, (int)(b / nbx), (int)(b % nbx),
+                             log_idx ? log_idx + b * (long)iters : NULL);
+    free(rp); free(all);
     return empty;
 }
 

@@ -9,15 +9,15 @@
 #include <stdlib.h>
 
 long fsro_reconstruct(const double *img, const uint8_t *mask, double *out, int H, int W, long stride,
-                      int B, int L, int iters, double rho, double gamma, int tie_larger, int decision,
+                      int B, int L, int iters, double rho, double gamma, int tie_larger,
                       uint16_t *log_idx, int threads);
 long fsro_reconstruct_blocks(const double *img, const uint8_t *mask, int H, int W, long stride, int B,
-                             int L, int iters, double rho, double gamma, int tie_larger, int decision,
+                             int L, int iters, double rho, double gamma, int tie_larger,
                              const int64_t *block_ids, long n, double *out_targets, uint16_t *log_idx,
                              double *log_p, int threads);
 long fsro_reconstruct_reuse(const double *img, const uint8_t *mask, double *out, int H, int W,
                             long stride, int B, int L, int iters, double rho, double gamma, double delta,
-                            int tie_larger, int decision, uint16_t *log_idx);
+                            int tie_larger, uint16_t *log_idx);
 
 static uint32_t state = 12345u;
 static uint32_t next(void) { state = state * 1664525u + 1013904223u; return state >> 8; }
@@ -34,10 +34,10 @@ static int run(int H, int W, long stride, int B, int L, int iters)
         img[i] = (double)(next() % 256);
         mask[i] = (uint8_t)(next() % 4 == 0);
     }
-    long e = fsro_reconstruct(img, mask, out, H, W, stride, B, L, iters, 0.7, 0.5, 0, 1, log, 2);
-    e += fsro_reconstruct_reuse(img, mask, out, H, W, stride, B, L, iters, 0.7, 0.5, 0.5, 0, 1, log);
+    long e = fsro_reconstruct(img, mask, out, H, W, stride, B, L, iters, 0.7, 0.5, 0, log, 2);
+    e += fsro_reconstruct_reuse(img, mask, out, H, W, stride, B, L, iters, 0.7, 0.5, 0.5, 0, log);
     int64_t ids[2] = {0, nb - 1};
-    e += fsro_reconstruct_blocks(img, mask, H, W, stride, B, L, iters, 0.7, 0.5, 0, 1, ids, 2, tg, log, lp, 2);
+    e += fsro_reconstruct_blocks(img, mask, H, W, stride, B, L, iters, 0.7, 0.5, 0, ids, 2, tg, log, lp, 2);
     printf("%dx%d stride %ld B=%d L=%d I=%d: %ld empty\n", H, W, stride, B, L, iters, e);
     free(img); free(out); free(mask); free(log); free(tg); free(lp);
     return 0;

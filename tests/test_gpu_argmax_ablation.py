@@ -40,8 +40,7 @@ def test_lds_argmax_small64_against_oracle(ctx):
     img, mask = w.inputs()
     img32 = img.astype(np.float32)
     g, gl = run(ctx, img32, mask, fsr.make_params(flags=fsr.FSR_FLAG_LDS_ARGMAX))
-    o, ol, _ = oracle.reconstruct(img32.astype(np.float64), mask, w.iterations, log=True,
-                                  decision=oracle.DECISION_KERNEL)
+    o, ol, _ = oracle.reconstruct(img32.astype(np.float64), mask, w.iterations, log=True)
     rep = parity_report(img32, mask, g, o, gl, ol)
     print(f"[parity] small64 lds-argmax: {rep}", flush=True)
     assert rep["known_bitwise"] and rep["frac_le_1"] >= 0.999 and rep["psnr_gap"] <= 0.05
@@ -87,8 +86,7 @@ def test_lds_argmax_at_smaller_supports(ctx, B, L):
     a, la = run(ctx, img, mask, reg)
     b, lb = run(ctx, img, mask, lds)
     assert np.array_equal(a, b) and np.array_equal(la, lb)
-    o, ol, _ = oracle.reconstruct(img.astype(np.float64), mask, 80, block_size=B, border=L, log=True,
-                                  decision=oracle.DECISION_KERNEL)
+    o, ol, _ = oracle.reconstruct(img.astype(np.float64), mask, 80, block_size=B, border=L, log=True)
     rep = parity_report(img, mask, b, o, lb, ol)
     print(f"[parity] S={S}: {rep}", flush=True)
     assert rep["known_bitwise"] and rep["frac_le_1"] >= 0.999 and rep["psnr_gap"] <= 0.05

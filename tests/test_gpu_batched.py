@@ -113,8 +113,7 @@ def test_batched_against_oracle(ctx):
     fsr.fsr_reconstruct_batched(ctx, items, fsr.make_params(), ws, fsr.make_schedule(1, 4, 10))
     got = results(items)
     for (img, mask, it), (g, gl) in zip(batch, got):
-        o, ol, _ = oracle.reconstruct(img.astype(np.float64), mask, it, log=True,
-                                      decision=oracle.DECISION_KERNEL)
+        o, ol, _ = oracle.reconstruct(img.astype(np.float64), mask, it, log=True)
         rep = parity_report(img, mask, g, o, gl if it else None, ol if it else None)
         print(f"[parity] batch image {img.shape} I={it}: {rep}", flush=True)
         assert rep["known_bitwise"] and rep["frac_le_1"] >= 0.999 and rep["psnr_gap"] <= 0.05
@@ -187,8 +186,7 @@ def test_synthetic_uneven_batch_sampled(ctx):
         img, mask, it = batch[k]
         n = fsr.fsr_num_blocks(img.shape[0], img.shape[1], 4)
         ids = np.sort(rng.choice(n, size=min(300, n), replace=False))
-        ot, ol, _, _ = oracle.reconstruct_blocks(img.astype(np.float64), mask, ids, it, log=True,
-                                                 decision=oracle.DECISION_KERNEL)
+        ot, ol, _, _ = oracle.reconstruct_blocks(img.astype(np.float64), mask, ids, it, log=True)
         g, gl = got[k]
         nbx = -(-img.shape[1] // 4)
         gt = np.stack([g[b // nbx * 4:b // nbx * 4 + 4, b % nbx * 4:b % nbx * 4 + 4] for b in ids])

@@ -7,16 +7,17 @@ Acceptance on every case (floating point path, FP32 on the GPU):
   * PSNR gap <= 0.05 dB;
   * the bin chosen at each logged (block, iteration) agrees with the oracle's
     on at least 99 % of them.
-Both sides receive the same float32 image (the oracle in float64), and the
-oracle takes its argmax decisions at the kernel's precision (float32
-objective, 4 low mantissa bits dropped, ties to the smaller bin); all its
-other arithmetic is FP64.
+Both sides receive the same float32 image (the oracle in float64).  The
+oracle is FP64 throughout, its argmax included (Eq. 8: the larger objective
+wins, exact ties go to the smaller bin).  The two benchmark frames are
+checked on every block.
 """
 import numpy as np
 import pytest
 
 import oracle
 import synth
+from tests.frames import oracle_frame
 from synth.metrics import parity_report
 
 torch = pytest.importorskip("torch")
@@ -29,7 +30,6 @@ TOL_CODE = 1.0
 FRAC = 0.999
 PSNR_GAP = 0.05
 ARGMAX = 0.99
-KERNEL = oracle.DECISION_KERNEL
 
 
 @pytest.fixture(scope="module")
@@ -68,17 +68,6 @@ def run_gpu(ctx, img, mask, params, stride=None, stream=None):
     return out.cpu().numpy(), lg.cpu().numpy().view(np.uint16)[:, :params.iterations]
 
 
-def block_targets(frame, ids, B):
-    H, W = frame.shape
-    nbx = -(-W // B)
-    t = np.full((len(ids), B, B), np.nan)
-    for i, b in enumerate(ids):
-        by, bx = divmod(int(b), nbx)
-        blk = frame[by * B:by * B + B, bx * B:bx * B + B]
-        t[i, :blk.shape[0], :blk.shape[1]] = blk
-    return t
-
-
 def assert_parity(rep, name):
     print(f"[parity] {name}: {rep}", flush=True)
     assert rep["known_bitwise"]
@@ -100,8 +89,7 @@ def test_small64_exhaustive(ctx):
     img, mask = w.inputs()
     img32 = img.astype(np.float32)
     g, gl = run_gpu(ctx, img32, mask, params_of(w))
-    o, ol, n_empty = oracle.reconstruct(img32.astype(np.float64), mask, w.iterations, log=True,
-                                        decision=KERNEL)
+    o, ol, n_empty = oracle.reconstruct(img32.astype(np.float64), mask, w.iterations, log=True)
     assert n_empty == 0
     rep = parity_report(img32, mask, g, o, gl, ol)
     assert_parity(rep, "small64")
@@ -109,34 +97,20 @@ def test_small64_exhaustive(ctx):
     assert np.array_equal(g[mask != 0], img32[mask != 0])
 
 
-def _sampled_ids(n_blocks, nbx, seed, k):
-    rng = np.random.default_rng(seed)
-    ids = set(rng.choice(n_blocks, size=k, replace=False).tolist())
-    nby = n_blocks // nbx
-    for by in (0, 1, nby // 2, nby - 2, nby - 1):      # border rows and columns
-        for bx in (0, 1, nbx // 2, nbx - 2, nbx - 1):
-            ids.add(by * nbx + bx)
-    return np.array(sorted(ids), np.int64)
-
-
-@pytest.mark.parametrize("name,k", [("fhd_quarter", 2500), ("uhd_concealment", 1200)])
-def test_full_size_frames_sampled(ctx, name, k):
-    announce(f"{name} full frame on the GPU, oracle on {k} sampled blocks")
+@pytest.mark.parametrize("name", ["fhd_quarter", "uhd_concealment"])
+def test_full_frames_every_block(ctx, name):
+    """The 1920x1080 quarter-sampled frame (I = 100, 129,600 blocks) and the
+    3840x2160 concealment frame (I = 200, 518,400 blocks), in the launch the
+    benchmark times, against the oracle on every block: every unknown pixel
+    and every logged (block, iteration)."""
+    announce(f"{name}: full frame on the GPU and in the oracle, every block")
     w = synth.workload(name)
-    img, mask = w.inputs()
-    img32 = img.astype(np.float32)
+    img32, mask, o, ol = oracle_frame(name)
     g, gl = run_gpu(ctx, img32, mask, params_of(w))
-    assert np.array_equal(g[mask != 0], img32[mask != 0])
     assert np.all(np.isfinite(g))
-    nbx = -(-w.width // w.block)
-    ids = _sampled_ids(w.n_blocks, nbx, 7, k)
-    ot, ol, _, _ = oracle.reconstruct_blocks(img32.astype(np.float64), mask, ids, w.iterations,
-                                             log=True, decision=KERNEL)
-    gt = block_targets(g, ids, w.block)
-    ref = block_targets(img32, ids, w.block)
-    mt = block_targets(mask.astype(np.float64), ids, w.block)
-    rep = parity_report(ref, mt, gt, ot, gl[ids], ol)
-    assert_parity(rep, name)
+    assert np.array_equal(g[mask != 0], img32[mask != 0])
+    rep = parity_report(img32, mask, g, o, gl, ol)
+    assert_parity(rep, f"{name} every block")
 
 
 def test_deterministic(ctx):
@@ -154,8 +128,7 @@ def _exhaustive(ctx, img, mask, params, stride=None, name=""):
     g, gl = run_gpu(ctx, img32, mask, params, stride=stride)
     o, ol, n_empty = oracle.reconstruct(img32.astype(np.float64), mask, params.iterations,
                                         block_size=params.block, border=params.border,
-                                        rho=params.rho, gamma=params.gamma, log=True,
-                                        decision=KERNEL)
+                                        rho=params.rho, gamma=params.gamma, log=True)
     rep = parity_report(img32, mask, g, o, gl if params.iterations else None,
                         ol if params.iterations else None)
     assert_parity(rep, name)
@@ -217,24 +190,18 @@ def test_tiny_images(ctx, H, W):
                                              (0.7, 0.5, 300)])
 def test_parameter_variants(ctx, rho, gamma, iters):
     """Parameters outside the stated workloads, on a 128 x 160 frame (1280
-    blocks).  Decisions are compared block by block: a block whose logged
-    choices all agree with the oracle's must match it to 1e-2 gray levels;
-    blocks that meet an FP32 near-tie and take another branch must stay rare
-    (<= 2 %), and the frame PSNR must agree within 0.05 dB."""
+    blocks), held to the same bars as the workloads.  The share of blocks
+    whose logged choices all agree with the oracle's is printed beside."""
     announce(f"rho = {rho}, gamma = {gamma}, I = {iters}")
     img, mask = synth.make_image(128, 160, 91), synth.quarter_mask(128, 160, 92)
     params = fsr.make_params(iterations=iters, rho=rho, gamma=gamma)
     img32 = img.astype(np.float32)
     g, gl = run_gpu(ctx, img32, mask, params)
     o, ol, _ = oracle.reconstruct(img32.astype(np.float64), mask, iters, rho=rho, gamma=gamma,
-                                  log=True, decision=KERNEL)
+                                  log=True)
     rep = parity_report(img32, mask, g, o, gl, ol)
-    print(f"[parity] variant rho{rho} gamma{gamma} I{iters}: {rep}", flush=True)
-    assert rep["known_bitwise"] and rep["psnr_gap"] <= PSNR_GAP
-    agree = np.all(gl == ol, axis=1).reshape(128 // 4, 160 // 4)
-    assert agree.mean() >= 0.98
-    err = np.abs(g - o).reshape(32, 4, 40, 4).max(axis=(1, 3))
-    assert np.all(err[agree] <= 1e-2)
+    rep["blocks_all_agree"] = float(np.all(gl == ol, axis=1).mean())
+    assert_parity(rep, f"variant rho{rho} gamma{gamma} I{iters}")
 
 
 def test_grid_sinusoid_recovered(ctx):
@@ -278,7 +245,7 @@ def test_flat_and_clipped_regions(ctx, dft):
     mask = synth.quarter_mask(H, W, 78)
     img32 = img.astype(np.float32)
     g, gl = run_gpu(ctx, img32, mask, fsr.make_params(iterations=60, dft=dft))
-    o, ol, _ = oracle.reconstruct(img32.astype(np.float64), mask, 60, log=True, decision=KERNEL)
+    o, ol, _ = oracle.reconstruct(img32.astype(np.float64), mask, 60, log=True)
     nbx = W // 4
     bx = np.arange(len(gl)) % nbx
     black = bx * 4 + 18 <= 40            # support entirely in the black band
@@ -325,7 +292,7 @@ def test_pixel_offsets_beyond_32_bits(ctx, B, L):
     del bi, bm, bo, ti, tm, to
     torch.cuda.empty_cache()
     o, ol, _ = oracle.reconstruct(img.astype(np.float64), mask, 40, block_size=B, border=L,
-                                  log=True, decision=KERNEL)
+                                  log=True)
     rep = parity_report(img, mask, g, o, gl, ol)
     assert_parity(rep, f"64-bit offsets S{B + 2 * L}")
     assert np.array_equal(g[mask != 0], img[mask != 0])

@@ -19,7 +19,6 @@ import paper_2202_13926_amd as fsr  # noqa: E402
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda:0"
-KERNEL = oracle.DECISION_KERNEL
 
 
 @pytest.fixture(scope="module")
@@ -49,7 +48,7 @@ def exhaustive(ctx, img, mask, B, L, iters, name, rho=0.7, gamma=0.5):
     p = fsr.make_params(block=B, border=L, iterations=iters, rho=rho, gamma=gamma)
     g, gl = run(ctx, img32, mask, p)
     o, ol, n_empty = oracle.reconstruct(img32.astype(np.float64), mask, iters, block_size=B,
-                                        border=L, rho=rho, gamma=gamma, log=True, decision=KERNEL)
+                                        border=L, rho=rho, gamma=gamma, log=True)
     check(parity_report(img32, mask, g, o, gl if iters else None, ol if iters else None), name)
     return g, gl, ol, n_empty
 
@@ -82,7 +81,7 @@ def test_s16_full_hd_sampled(ctx):
     n = fsr.fsr_num_blocks(1080, 1920, 4)
     ids = np.array(sorted(np.random.default_rng(21).choice(n, size=3000, replace=False).tolist()))
     ot, ol, _, _ = oracle.reconstruct_blocks(img32.astype(np.float64), mask, ids, 100, block_size=4,
-                                             border=6, log=True, decision=KERNEL)
+                                             border=6, log=True)
 
     def targets(frame):
         t = np.full((len(ids), 4, 4), np.nan)

@@ -14,6 +14,7 @@ import pytest
 
 import oracle
 import synth
+from tests.frames import oracle_frame
 from synth.metrics import parity_report
 
 torch = pytest.importorskip("torch")
@@ -25,7 +26,6 @@ DEV = "cuda:0"
 TOL_FRAC = 0.999
 PSNR_GAP = 0.05
 ARGMAX = 0.99
-KERNEL = oracle.DECISION_KERNEL
 BF16 = fsr.FSR_DFT_SPLIT_BF16
 
 
@@ -60,50 +60,31 @@ def check(rep, name):
         assert rep["argmax_agree"] >= ARGMAX
 
 
-def block_targets(frame, ids, B):
-    H, W = frame.shape
-    nbx = -(-W // B)
-    t = np.full((len(ids), B, B), np.nan)
-    for i, b in enumerate(ids):
-        by, bx = divmod(int(b), nbx)
-        blk = frame[by * B:by * B + B, bx * B:bx * B + B]
-        t[i, :blk.shape[0], :blk.shape[1]] = blk
-    return t
-
-
 def test_small64_against_oracle(ctx):
     announce("split-bf16 DFT: small64 64x64 quarter I=100, every pixel")
     w = synth.workload("small64")
     img, mask = w.inputs()
     img32 = img.astype(np.float32)
-    o, ol, _ = oracle.reconstruct(img32.astype(np.float64), mask, w.iterations, log=True,
-                                  decision=KERNEL)
+    o, ol, _ = oracle.reconstruct(img32.astype(np.float64), mask, w.iterations, log=True)
     for dft, tag in ((fsr.FSR_DFT_FP32, "fp32"), (BF16, "split-bf16")):
         g, gl = run(ctx, img32, mask, params_of(w, dft))
         rep = parity_report(img32, mask, g, o, gl, ol)
         check(rep, f"small64 {tag}")
 
 
-@pytest.mark.parametrize("name,k", [("fhd_quarter", 2500), ("uhd_concealment", 1200)])
-def test_full_frames_sampled(ctx, name, k):
-    announce(f"split-bf16 DFT: {name} full frame, oracle on {k} sampled blocks")
+@pytest.mark.parametrize("name", ["fhd_quarter", "uhd_concealment"])
+def test_full_frames_every_block(ctx, name):
+    """The 1080p quarter frame (I = 100) and the 2160p concealment frame
+    (I = 200) through both DFT modes, each against the oracle on every block
+    and every logged (block, iteration)."""
+    announce(f"split-bf16 DFT: {name}, full frame, every block, beside the FP32 FFTs")
     w = synth.workload(name)
-    img, mask = w.inputs()
-    img32 = img.astype(np.float32)
-    nbx = -(-w.width // w.block)
-    rng = np.random.default_rng(11)
-    ids = np.array(sorted(rng.choice(w.n_blocks, size=k, replace=False).tolist()), np.int64)
-    ot, ol, _, _ = oracle.reconstruct_blocks(img32.astype(np.float64), mask, ids, w.iterations,
-                                             log=True, decision=KERNEL)
-    ref = block_targets(img32, ids, w.block)
-    mt = block_targets(mask.astype(np.float64), ids, w.block)
-    reps = {}
+    img32, mask, o, ol = oracle_frame(name)
     for dft, tag in ((fsr.FSR_DFT_FP32, "fp32"), (BF16, "split-bf16")):
         g, gl = run(ctx, img32, mask, params_of(w, dft))
         assert np.array_equal(g[mask != 0], img32[mask != 0])
         assert np.all(np.isfinite(g))
-        reps[tag] = parity_report(ref, mt, block_targets(g, ids, w.block), ot, gl[ids], ol)
-        check(reps[tag], f"{name} {tag}")
+        check(parity_report(img32, mask, g, o, gl, ol), f"{name} {tag} every block")
 
 
 def test_edge_cases_against_oracle(ctx):
@@ -113,8 +94,7 @@ def test_edge_cases_against_oracle(ctx):
     img32 = img.astype(np.float32)
     p = fsr.make_params(iterations=40, dft=BF16)
     g, gl = run(ctx, img32, mask, p)
-    o, ol, n_empty = oracle.reconstruct(img32.astype(np.float64), mask, 40, log=True,
-                                        decision=KERNEL)
+    o, ol, n_empty = oracle.reconstruct(img32.astype(np.float64), mask, 40, log=True)
     assert n_empty > 0
     check(parity_report(img32, mask, g, o, gl, ol), "hole 96x100")
     assert np.all(gl[np.all(ol == 0xFFFF, axis=1)] == 0xFFFF)

@@ -33,9 +33,10 @@ MUTANTS = {
                         "out_target[i * B + j] = !known[m * S + n] ? ft[m * S + n]"),
     "projection_not_normalised": ("const double p_re = Rr[best] / w00, p_im = Ri[best] / w00;",
                                   "const double p_re = Rr[best] / (2.0 * w00), p_im = Ri[best] / (2.0 * w00);"),
-    "objective_without_freq_weight": ("decision_value(wf[b] * (Rr[b] * Rr[b] + Ri[b] * Ri[b]), decision)",
-                                      "decision_value((Rr[b] * Rr[b] + Ri[b] * Ri[b]), decision)"),
-    "kernel_decision_keeps_low_bits": ("u &= ~(uint32_t)0xF;", "u &= ~(uint32_t)0x0;"),
+    "objective_without_freq_weight": ("double obj = wf[b] * (Rr[b] * Rr[b] + Ri[b] * Ri[b]);",
+                                      "double obj = (Rr[b] * Rr[b] + Ri[b] * Ri[b]);"),
+    "objective_rounded_to_float32": ("double obj = wf[b] * (Rr[b] * Rr[b] + Ri[b] * Ri[b]);",
+                                     "double obj = (float)(wf[b] * (Rr[b] * Rr[b] + Ri[b] * Ri[b]));"),
 }
 
 PIN_CALLS = [
@@ -56,8 +57,7 @@ PIN_CALLS = [
     pins.test_fully_known_image_unchanged,
     pins.test_known_pixels_copied_bitwise,
     pins.test_zero_iterations_gives_zero_model,
-    pins.test_kernel_precision_decision,
-    pins.test_kernel_precision_breaks_sub_resolution_ties_by_index,
+    pins.test_fp64_decision_resolves_sub_float32_differences,
 ]
 
 

@@ -388,52 +388,35 @@ def test_threads_do_not_change_results(oracle_lib):
 
 
 # ---------------------------------------------------------------- decision precision
-def test_kernel_precision_decision(oracle_lib):
-    """decision = 1 compares float32(objective) with its 4 lowest mantissa bits
-    cleared, ties to the smaller bin; recomputed here with numpy for the first
-    pick of blocks built to have near-ties below that resolution."""
-    S = 32
-    hits = 0
-    for seed in range(40):
-        ft, known = random_support(S, 500 + seed)
-        w = np_weight(known, 0.7)
-        R0 = np.fft.fft2(ft * w)
-        obj = np_freq_weight(S) * np.abs(R0) ** 2
-        key = (obj.astype(np.float32).view(np.uint32) & np.uint32(0xFFFFFFF0)).ravel()
-        expect = int(np.flatnonzero(key == key.max()).min())
-        res = oracle_lib.block(ft, known, 1, 0.7, 0.5, decision=oracle_lib.DECISION_KERNEL)
-        assert int(res["idx"][0]) == expect
-        hits += 1
-    assert hits == 40
-
-
-def test_kernel_precision_breaks_sub_resolution_ties_by_index(oracle_lib):
-    """All pixels known and rho = 1 make W = S^2 delta, so R0 = DFT2(f) and the
-    objectives of f = A cos(2 pi n/S) + alpha A cos(2 pi m/S) at bins (0,1)
-    and (1,0) differ by the factor alpha^2.  With alpha - 1 ~ 1e-7 the FP64
-    decision takes (1,0) (index 32) while at kernel precision both share one
-    key and the smaller index 1 wins."""
+def test_fp64_decision_resolves_sub_float32_differences(oracle_lib):
+    """Eq. 8 is a plain argmax: the oracle must compare its FP64 objectives as
+    they are.  All pixels known and rho = 1 make W = S^2 delta, so R0 =
+    DFT2(f) and the objectives of f = A cos(2 pi n/S) + alpha A cos(2 pi m/S)
+    at bins (0,1) and (1,0) differ by exactly the factor alpha^2 (closed
+    form).  For alpha within a few 1e-8 of 1 the two objectives round to the
+    same float32 value; the larger must still win: (1,0) (index 32) when
+    alpha > 1, (0,1) (index 1) when alpha < 1, and with alpha = 1 they tie
+    exactly and the smaller index 1 wins."""
     S, A = 32, 50.0
     m = np.arange(S)
     known = np.ones((S, S), np.uint8)
     wf = np_freq_weight(S)
 
-    def key(x):
-        return int(np.float32(x).view(np.uint32)) & 0xFFFFFFF0
-
-    chosen = None
-    for step in range(1, 400):
-        alpha = 1.0 + step * 2e-8
+    def objectives(alpha):
         f = A * np.cos(2 * np.pi * m[None, :] / S) + alpha * A * np.cos(2 * np.pi * m[:, None] / S)
         obj = wf * np.abs(np.fft.fft2(f)) ** 2
-        a, b = obj[0, 1], obj[1, 0]
-        # same key, FP64 order b > a, and away from a float32 rounding boundary
-        fa = np.float32(a)
-        if key(a) == key(b) and b > a * (1 + 1e-9) and key(np.nextafter(fa, np.float32(0))) == key(a) \
-                and key(np.nextafter(np.float32(b), np.float32(np.inf))) == key(b):
-            chosen = f
-            break
-    assert chosen is not None
-    r0 = oracle_lib.block(chosen, known, 1, 1.0, 0.5, decision=oracle_lib.DECISION_FP64)
-    r1 = oracle_lib.block(chosen, known, 1, 1.0, 0.5, decision=oracle_lib.DECISION_KERNEL)
-    assert int(r0["idx"][0]) == 32 and int(r1["idx"][0]) == 1
+        return f, obj[0, 1], obj[1, 0]
+
+    cases = [(1.0, 1)]
+    for sign, expect in ((1.0, 32), (-1.0, 1)):
+        for step in range(1, 200):
+            alpha = 1.0 + sign * step * 5e-9
+            f, a, b = objectives(alpha)
+            if np.float32(a) == np.float32(b) and abs(b - a) > 1e-9 * a:
+                cases.append((alpha, expect))
+                break
+    assert len(cases) == 3
+    for alpha, expect in cases:
+        f, _, _ = objectives(alpha)
+        r = oracle_lib.block(f, known, 1, 1.0, 0.5)
+        assert int(r["idx"][0]) == expect, (alpha, int(r["idx"][0]))

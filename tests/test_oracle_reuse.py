@@ -12,8 +12,10 @@ reuse, a uniform scaling of the weights changes nothing (Eqs. 7, 10 and 8 are
 homogeneous in w), a brute-force restatement of the raster definition built
 from block ownership, and causality (a change reaches earlier blocks only
 through their own supports; with reuse, also the blocks after the first one
-that sees it).  Planted slips
-in a copy of the C source must fail at least one of them.
+that sees it).  The per-block form (`reconstruct_reuse_given`, each block
+handed the frame its reused pixels come from) is pinned to the scan itself
+and to exactly which blocks a reused pixel reaches.  Planted slips in a copy
+of the C source must fail at least one of them.
 """
 import os
 import subprocess
@@ -189,6 +191,71 @@ def test_crop_blocks_see_the_full_frame(oracle_lib):
     assert not np.array_equal(full[:Hc, :Wc][~sel], crop[~sel])
 
 
+# ---------------------------------------------------------------- each block given the reused frame
+GIVEN_CASES = [
+    (64, 64, "quarter", 4, 14, 100, 0.5),
+    (22, 18, "quarter", 2, 3, 25, 1.0),
+    (40, 52, "macroblock", 4, 6, 60, 0.25),
+    (37, 9, "uniform:0.4", 4, 14, 40, 0.5),
+]
+
+
+@pytest.mark.parametrize("case", GIVEN_CASES)
+def test_given_own_output_reproduces_the_sequential_scan(oracle_lib, case):
+    """Each block of the scan reads its reused pixels from blocks that are
+    final by then, so handing every block the scan's own finished frame gives
+    each one the very inputs it had inside the scan: output and log bitwise
+    equal, for square, wide and one-column frames and every mask kind."""
+    H, W, mk, B, L, iters, delta = case
+    img = synth.make_image(H, W, 3100 + H)
+    mask = synth.make_mask(mk, H, W, 3200 + W)
+    seq, ls, es = oracle_lib.reconstruct_reuse(img, mask, iters, delta=delta, block_size=B,
+                                               border=L, log=True)
+    got, lg, eg = oracle_lib.reconstruct_reuse_given(img, mask, seq, iters, delta=delta,
+                                                     block_size=B, border=L, log=True)
+    assert np.array_equal(got, seq) and np.array_equal(lg, ls) and eg == es
+
+
+def test_given_delta_zero_is_the_block_independent_method(oracle_lib):
+    img, mask = synth.workload("small64").inputs()
+    junk = np.full(img.shape, 1.0e6)
+    a, la, _ = oracle_lib.reconstruct(img, mask, 40, log=True)
+    b, lb, _ = oracle_lib.reconstruct_reuse_given(img, mask, junk, 40, delta=0.0, log=True)
+    assert np.array_equal(a, b) and np.array_equal(la, lb)
+
+
+def test_given_frame_reaches_exactly_the_later_supports(oracle_lib):
+    """A change of the given frame at a known pixel changes nothing (known
+    pixels come from the input).  A change at a missing pixel p changes
+    exactly the blocks that reuse p: those whose support holds p and that
+    come after p's own block in raster order (Sec. II's original method
+    reuses only what earlier blocks reconstructed)."""
+    B, L, H, W = 4, 6, 48, 56
+    img, mask = synth.make_image(H, W, 71), synth.quarter_mask(H, W, 72)
+    base, _, _ = oracle_lib.reconstruct_reuse(img, mask, 30, delta=0.5, block_size=B, border=L)
+    a, _, _ = oracle_lib.reconstruct_reuse_given(img, mask, base, 30, delta=0.5, block_size=B,
+                                                 border=L)
+    nby, nbx = H // B, W // B
+    ky, kx = np.argwhere(mask[20:24, 24:28] != 0)[0] + (20, 24)
+    moved = base.copy()
+    moved[ky, kx] += 50.0
+    b, _, _ = oracle_lib.reconstruct_reuse_given(img, mask, moved, 30, delta=0.5, block_size=B,
+                                                 border=L)
+    assert np.array_equal(a, b)
+    py, px = np.argwhere(mask[20:24, 24:28] == 0)[0] + (20, 24)
+    moved = base.copy()
+    moved[py, px] += 50.0
+    b, _, _ = oracle_lib.reconstruct_reuse_given(img, mask, moved, 30, delta=0.5, block_size=B,
+                                                 border=L)
+    own = (py // B) * nbx + px // B
+    for by in range(nby):
+        for bx in range(nbx):
+            t = (slice(by * B, by * B + B), slice(bx * B, bx * B + B))
+            inside = by * B - L <= py < by * B + B + L and bx * B - L <= px < bx * B + B + L
+            reuses = inside and by * nbx + bx > own
+            assert np.array_equal(a[t], b[t]) != reuses, (by, bx)
+
+
 # ---------------------------------------------------------------- sensitivity
 def perturbed_spread(o, img, mask, iters, delta, B, L, seeds=(0, 1, 2), sel=None, rel=1e-6):
     """How far the reuse variant moves when the known pixels change by a
@@ -199,14 +266,13 @@ def perturbed_spread(o, img, mask, iters, delta, B, L, seeds=(0, 1, 2), sel=None
     (and the argmax to the blocks it covers)."""
     from synth.metrics import parity_report
     H, W = img.shape
-    a, la, _ = o.reconstruct_reuse(img, mask, iters, delta=delta, block_size=B, border=L, log=True,
-                                   decision=o.DECISION_KERNEL)
+    a, la, _ = o.reconstruct_reuse(img, mask, iters, delta=delta, block_size=B, border=L, log=True)
     worst = {"frac_le_1": 1.0, "argmax_agree": 1.0, "psnr_gap": 0.0}
     for s in seeds:
         rng = np.random.default_rng(s)
         pert = img * (1.0 + rel * rng.standard_normal(img.shape))
         b, lb, _ = o.reconstruct_reuse(pert, mask, iters, delta=delta, block_size=B, border=L,
-                                       log=True, decision=o.DECISION_KERNEL)
+                                       log=True)
         if sel is None:
             rep = parity_report(img, mask, b, a, lb, la)
         else:
@@ -235,8 +301,8 @@ def test_reuse_amplifies_rounding_level_changes(oracle_lib):
     assert chaotic["psnr_gap"] <= 0.05                 # the quality does not move
     rng = np.random.default_rng(0)
     pert = img * (1.0 + 1e-6 * rng.standard_normal(img.shape))
-    _, la, _ = oracle_lib.reconstruct(img, mask, 100, log=True, decision=oracle_lib.DECISION_KERNEL)
-    _, lb, _ = oracle_lib.reconstruct(pert, mask, 100, log=True, decision=oracle_lib.DECISION_KERNEL)
+    _, la, _ = oracle_lib.reconstruct(img, mask, 100, log=True)
+    _, lb, _ = oracle_lib.reconstruct(pert, mask, 100, log=True)
     assert (la != lb).any(axis=1).sum() <= 2
     for (H, W, mk, B, L, iters, delta) in STABLE_CASES:
         img = synth.make_image(H, W, 2100 + H).astype(np.float32).astype(np.float64)
@@ -263,8 +329,12 @@ MUTANTS = {
                            "const int earlier = x < bx * B || (x < (bx + 1) * B && y < by * B);"),
     "reuses_current_block": ("const int earlier = y < by * B || (y < (by + 1) * B && x < bx * B);",
                              "const int earlier = y < by * B || (y < (by + 1) * B && x < (bx + 1) * B);"),
-    "reused_value_from_input": ("reused ? out[(long)y * stride + x] : 0.0;",
+    "reused_value_from_input": ("reused ? src[(long)y * stride + x] : 0.0;",
                                 "reused ? img[(long)y * stride + x] : 0.0;"),
+    "given_frame_ignored": ("empty += reuse_block(img, mask, reused, out,",
+                            "empty += reuse_block(img, mask, img, out,"),
+    "given_blocks_shifted": ("tie_larger, (int)(b / nbx), (int)(b % nbx),",
+                             "tie_larger, (int)(b % nbx), (int)(b / nbx),"),
     "reused_weight_without_delta": ("reused ? delta * rp[i] : 0.0;", "reused ? rp[i] : 0.0;"),
     "delta_on_known_pixels": ("w[i] = k ? rp[i] :", "w[i] = k ? delta * rp[i] :"),
 }
@@ -276,6 +346,9 @@ PIN_CALLS = [
     lambda o: test_bruteforce_raster_definition(o, 0.5, 4, 6),
     lambda o: test_changes_reach_later_blocks_only_through_reuse(o, 0.5),
     test_reuse_keeps_known_pixels_and_fully_known_images,
+    lambda o: test_given_own_output_reproduces_the_sequential_scan(o, GIVEN_CASES[1]),
+    test_given_delta_zero_is_the_block_independent_method,
+    test_given_frame_reaches_exactly_the_later_supports,
 ]
 
 
