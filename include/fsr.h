@@ -254,6 +254,30 @@ FSR_API fsr_status fsr_reconstruct_batched(fsr_context *ctx, const fsr_image_des
                                            const fsr_batch_schedule *schedule, void *workspace,
                                            size_t workspace_bytes, void *stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * reconstruction as fsr_reconstruct_batched with the same schedule argument,
+ * bitwise the same outputs and logs, without a caller workspace and without
+ * allocating anything.  The queue head and the descriptor table live in a
+ * fixed device array of the library, FSR_NOALLOC_WORKSPACE_BYTES bytes on
+ * each device (looked up when a context is created there, held until the
+ * process ends), so a call takes at most FSR_NOALLOC_MAX_IMAGES images
+ * (FSR_ERR_INVALID_ARG beyond).  The context must already hold the tables
+ * of this support and rho (built by an earlier fsr_reconstruct or
+ * fsr_reconstruct_batched call with them); else FSR_ERR_UNSUPPORTED and
+ * nothing is enqueued.  Every call on a device shares that device's array
+ * and overwrites what the previous call left there (the queue head is reset
+ * by each launch): calls whose work can overlap on one device (other
+ * streams, other contexts or threads) race, and the caller must order them,
+ * e.g. on one stream.  Asynchronous on `stream`.
+ */
+#define FSR_NOALLOC_MAX_IMAGES 64
+#define FSR_NOALLOC_WORKSPACE_BYTES (256 + 64 * FSR_NOALLOC_MAX_IMAGES)
+FSR_API fsr_status fsr_reconstruct_batched_noalloc(fsr_context *ctx, const fsr_image_desc *descs,
+                                                   int32_t n_images, const fsr_params *params,
+                                                   const fsr_batch_schedule *schedule, void *stream);
+
 /* Times the batch under candidate schedules: a fixed list plus persistent
  * schedules sized to the number of workgroups a compute unit holds for this
  * support and dft mode.  Each run reconstructs the batch, so outputs are

@@ -29,6 +29,8 @@ FSR_DFT_SPLIT_BF16 = 1
 
 FSR_FLAG_LDS_ARGMAX = 1
 
+FSR_NOALLOC_MAX_IMAGES = 64
+
 
 class FsrError(RuntimeError):
     def __init__(self, status: int, message: str):
@@ -139,6 +141,8 @@ def load_library(path: str | None = None):
         "fsr_reconstruct_batched": (ctypes.c_int, [vp, ctypes.POINTER(fsr_image_desc), i32, P,
                                                    ctypes.POINTER(fsr_batch_schedule), vp,
                                                    ctypes.c_size_t, vp]),
+        "fsr_reconstruct_batched_noalloc": (ctypes.c_int, [vp, ctypes.POINTER(fsr_image_desc), i32, P,
+                                                           ctypes.POINTER(fsr_batch_schedule), vp]),
         "fsr_batch_autotune": (ctypes.c_int, [vp, ctypes.POINTER(fsr_image_desc), i32, P, vp,
                                               ctypes.c_size_t, vp,
                                               ctypes.POINTER(fsr_batch_schedule)]),
@@ -442,6 +446,19 @@ def fsr_reconstruct_batched(ctx: Context, items, params: fsr_params, workspace: 
     _check(load_library().fsr_reconstruct_batched(
         ctx.handle, descs, len(items), ctypes.byref(params), sched, workspace.ptr,
         workspace.nbytes, _stream_handle(stream, dev) if dev is not None else None))
+
+
+def fsr_reconstruct_batched_noalloc(ctx: Context, items, params: fsr_params,
+                                    schedule: fsr_batch_schedule | None = None, stream=None) -> None:
+    """fsr_reconstruct_batched without a workspace and without any allocation
+    (at most FSR_NOALLOC_MAX_IMAGES images; the context must hold the tables
+    of this support and rho already)."""
+    descs = _descs(items, params.block)
+    dev = items[0].image.device if items else None
+    sched = ctypes.byref(schedule) if schedule is not None else None
+    _check(load_library().fsr_reconstruct_batched_noalloc(
+        ctx.handle, descs, len(items), ctypes.byref(params), sched,
+        _stream_handle(stream, dev) if dev is not None else None))
 
 
 def fsr_batch_autotune(ctx: Context, items, params: fsr_params, workspace: Workspace,

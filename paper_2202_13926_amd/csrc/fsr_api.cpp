@@ -273,6 +273,18 @@ fsr_status context_tables(fsr_context* ctx, int S, float rho, BlockTables* out, 
     std::lock_guard<std::mutex> lock(ctx->mu);
     fsr_status st;
     *out = BlockTables{};
+    uint32_t bits;
+    std::memcpy(&bits, &rho, sizeof bits);
+    const uint64_t key = ((uint64_t)(uint32_t)S << 32) | bits;
+    if (!may_build) {
+        // look the tables up without inserting (a map insertion allocates)
+        const bool have = ctx->freq_w.count(S) && ctx->rho_pow.count(key) &&
+                          (S == kS ? ctx->mfma_tab != nullptr : ctx->dft_sg.count(S) != 0);
+        if (!have)
+            return fail(FSR_ERR_UNSUPPORTED,
+                        "the tables of support %d and rho %g are not on the context yet: make one "
+                        "call with these parameters that may build them first", S, (double)rho);
+    }
     if ((st = device_table(&ctx->freq_w[S], may_build, "frequency table", S, rho,
                            [&] { return host_freq_w(S); })) != FSR_OK)
         return st;
@@ -286,9 +298,6 @@ fsr_status context_tables(fsr_context* ctx, int S, float rho, BlockTables* out, 
         st = device_table(&ctx->dft_sg[S], may_build, "dft table", S, rho, [&] { return host_dft_sg(S); });
     }
     if (st != FSR_OK) return st;
-    uint32_t bits;
-    std::memcpy(&bits, &rho, sizeof bits);
-    const uint64_t key = ((uint64_t)(uint32_t)S << 32) | bits;
     if ((st = device_table(&ctx->rho_pow[key], may_build, "weight table", S, rho,
                            [&] { return host_rho_pow(S, rho); })) != FSR_OK)
         return st;
@@ -353,6 +362,13 @@ fsr_status fsr_context_create(fsr_context** out, int32_t device) {
     if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
     if (device < 0 || device >= n)
         return fail(FSR_ERR_INVALID_ARG, "device %d out of range (%d devices)", device, n);
+    {
+        // the device address of the fixed workspace of
+        // fsr_reconstruct_batched_noalloc, looked up once per device
+        DeviceGuard g(device);
+        if (g.error() != hipSuccess) return hip_fail(g.error(), "hipSetDevice");
+        if ((e = static_workspace_init(device)) != hipSuccess) return hip_fail(e, "hipGetSymbolAddress");
+    }
     fsr_context* ctx = new (std::nothrow) fsr_context();
     if (!ctx) return fail(FSR_ERR_OUT_OF_MEMORY, "context allocation failed");
     ctx->device = device;

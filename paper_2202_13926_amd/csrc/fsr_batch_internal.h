@@ -2,6 +2,7 @@
 // host runtime and its kernels.
 #pragma once
 
+#include "fsr.h"
 #include "fsr_internal.h"
 
 namespace fsr {
@@ -55,6 +56,25 @@ hipError_t launch_batched(const BatchLaunch& p, int waves_per_group, int64_t gro
 // copies lets a small batch run beside a large one.
 constexpr int kDescsPerKernel = 16;    // descriptors carried by one kernel's arguments
 constexpr int kDescKernelMax = 64;     // larger tables go through a pinned copy
+
+// Bytes of a batch workspace ahead of its descriptor table: the queue head,
+// padded.
+constexpr size_t kQueueCtrlBytes = 256;
+
+// The fixed workspace of fsr_reconstruct_batched_noalloc: a device array of
+// the library (one copy per device) holding the queue head and the
+// descriptors of at most kStaticImages images.
+constexpr int kStaticImages = FSR_NOALLOC_MAX_IMAGES;
+constexpr size_t kStaticWorkspaceBytes = kQueueCtrlBytes + kStaticImages * sizeof(DevDesc);
+static_assert(kStaticImages <= kDescKernelMax, "the descriptors of a fixed-workspace batch travel by kernel");
+
+// Looks up the device address of that array on `device`, which the caller
+// has made current, once per device (later calls return at once).
+hipError_t static_workspace_init(int device);
+
+// That address on `device`, or nullptr if static_workspace_init has not
+// succeeded there.
+void* static_workspace(int device);
 
 // Writes the n <= kDescKernelMax descriptors of `table` to `dst` (device)
 // with kernels on `stream`.

@@ -16,7 +16,7 @@ namespace fsr {
 
 namespace {
 
-constexpr size_t kCtrlBytes = 256;                 // queue head, padded
+constexpr size_t kCtrlBytes = kQueueCtrlBytes;
 constexpr int64_t kMaxBlocks = int64_t(1) << 30;   // keeps the 32-bit queue head from wrapping
 constexpr int kMaxGroupsPerCu = 32;                // a compute unit holds at most 32 wavefronts
 
@@ -24,11 +24,16 @@ size_t workspace_bytes_for(int32_t n) {
     return kCtrlBytes + ((size_t)n * sizeof(DevDesc) + 255) / 256 * 256;
 }
 
-struct BatchPlan {
-    std::vector<DevDesc> table;   // queue order
+// What the schedule choice needs to know about a planned batch.
+struct PlanTotals {
     int64_t total_blocks = 0;
     double work = 0.0;            // sum over images of blocks x iterations
     int32_t max_iterations = 0;
+};
+
+struct BatchPlan {
+    std::vector<DevDesc> table;   // queue order
+    PlanTotals totals;
 };
 
 fsr_status check_schedule(const fsr_batch_schedule* s) {
@@ -44,15 +49,11 @@ fsr_status check_schedule(const fsr_batch_schedule* s) {
     return FSR_OK;
 }
 
-fsr_status plan_batch(const fsr_image_desc* descs, int32_t n, const fsr_params* params,
-                      BatchPlan* plan) {
+// Validates every descriptor and stores its block count in blocks[i].
+fsr_status check_images(const fsr_image_desc* descs, int32_t n, const fsr_params* params, int64_t* blocks) {
     if (n < 0) return errorf(FSR_ERR_INVALID_ARG, "n_images must be >= 0 (got %d)", n);
     if (n > 0 && !descs) return errorf(FSR_ERR_INVALID_ARG, "descs is NULL");
     const int B = params->block;
-    // blocks per wavefront: each image's range in the index space is padded
-    // to a multiple of it, so that no wavefront spans two images
-    const int64_t unit = batch_unit(params->block + 2 * params->border, B);
-    std::vector<int64_t> blocks(n);
     for (int32_t i = 0; i < n; ++i) {
         const fsr_image_desc& d = descs[i];
         fsr_status st = validate_image(d.image, d.mask, d.out, d.height, d.width, d.stride, B);
@@ -61,18 +62,31 @@ fsr_status plan_batch(const fsr_image_desc* descs, int32_t n, const fsr_params* 
         if (d.reserved != 0) return errorf(FSR_ERR_INVALID_ARG, "image %d: reserved must be 0", i);
         blocks[i] = fsr_num_blocks(d.height, d.width, B);
     }
-    // queue order: decreasing iterations, then decreasing size, then input order
-    std::vector<int32_t> order(n);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    return FSR_OK;
+}
+
+// Queue order: decreasing iterations, then decreasing size, then input order.
+struct QueueOrder {
+    const fsr_image_desc* descs;
+    const int64_t* blocks;
+    bool operator()(int32_t a, int32_t b) const {
         if (descs[a].iterations != descs[b].iterations) return descs[a].iterations > descs[b].iterations;
         return blocks[a] > blocks[b];
-    });
-    plan->table.resize(n);
+    }
+};
+
+// Fills table[0..n) in the queue order `order` and the totals.
+fsr_status fill_table(const fsr_image_desc* descs, int32_t n, const fsr_params* params, const int32_t* order,
+                      const int64_t* blocks, DevDesc* table, PlanTotals* tot) {
+    const int B = params->block;
+    // blocks per wavefront: each image's range in the index space is padded
+    // to a multiple of it, so that no wavefront spans two images
+    const int64_t unit = batch_unit(params->block + 2 * params->border, B);
+    *tot = PlanTotals{};
     int64_t begin = 0;
     for (int32_t j = 0; j < n; ++j) {
         const fsr_image_desc& d = descs[order[j]];
-        DevDesc& e = plan->table[j];
+        DevDesc& e = table[j];
         e.image = d.image;
         e.mask = d.mask;
         e.out = d.out;
@@ -84,18 +98,30 @@ fsr_status plan_batch(const fsr_image_desc* descs, int32_t n, const fsr_params* 
         e.iterations = d.iterations;
         e.nbx = (d.width + B - 1) / B;
         begin += (blocks[order[j]] + unit - 1) / unit * unit;
-        plan->work += (double)blocks[order[j]] * (double)(d.iterations + 8);
-        plan->max_iterations = std::max(plan->max_iterations, d.iterations);
+        tot->work += (double)blocks[order[j]] * (double)(d.iterations + 8);
+        tot->max_iterations = std::max(tot->max_iterations, d.iterations);
     }
     if (begin > kMaxBlocks) return errorf(FSR_ERR_UNSUPPORTED, "a batch may hold at most 2^30 blocks");
-    plan->total_blocks = begin;
+    tot->total_blocks = begin;
     return FSR_OK;
+}
+
+fsr_status plan_batch(const fsr_image_desc* descs, int32_t n, const fsr_params* params,
+                      BatchPlan* plan) {
+    std::vector<int64_t> blocks(n > 0 ? n : 0);
+    fsr_status st = check_images(descs, n, params, blocks.data());
+    if (st != FSR_OK) return st;
+    std::vector<int32_t> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), QueueOrder{descs, blocks.data()});
+    plan->table.resize(n);
+    return fill_table(descs, n, params, order.data(), blocks.data(), plan->table.data(), &plan->totals);
 }
 
 // Key of the tuned-schedule table: log2 of the batch's work, the support
 // size and the DFT mode (the kernels differ in register and LDS use) and the
 // largest iteration count.
-uint64_t size_class(const BatchPlan& plan, const fsr_params& params) {
+uint64_t size_class(const PlanTotals& plan, const fsr_params& params) {
     uint64_t w = 0;
     for (double x = plan.work; x >= 2.0; x /= 2.0) ++w;
     const uint64_t S = (uint64_t)(params.block + 2 * params.border);
@@ -123,10 +149,8 @@ struct Prepared {
     int64_t groups = 0;
 };
 
-// Everything common to eager launches, autotuning and graph capture.
-fsr_status prepare(fsr_context* ctx, const fsr_image_desc* descs, int32_t n, const fsr_params* params,
-                   const fsr_batch_schedule* schedule, void* workspace, size_t ws_bytes,
-                   BatchPlan* plan, Prepared* prep) {
+// Checks of the parameters and the schedule, before any image is looked at.
+fsr_status check_batch_params(fsr_context* ctx, const fsr_params* params, const fsr_batch_schedule* schedule) {
     if (!ctx) return errorf(FSR_ERR_INVALID_ARG, "context is NULL");
     fsr_status st = validate_params(params);
     if (st != FSR_OK) return st;
@@ -136,15 +160,18 @@ fsr_status prepare(fsr_context* ctx, const fsr_image_desc* descs, int32_t n, con
     const int S = params->block + 2 * params->border;
     if (S != kS && params->dft != FSR_DFT_FP32)
         return errorf(FSR_ERR_UNSUPPORTED, "support %d runs with FSR_DFT_FP32 only", S);
-    if ((st = check_schedule(schedule)) != FSR_OK) return st;
-    if ((st = plan_batch(descs, n, params, plan)) != FSR_OK) return st;
-    if (!workspace && n > 0) return errorf(FSR_ERR_INVALID_ARG, "workspace is NULL");
-    if (ws_bytes < workspace_bytes_for(n))
-        return errorf(FSR_ERR_INVALID_ARG, "workspace of %zu bytes is smaller than the %zu needed",
-                      ws_bytes, workspace_bytes_for(n));
+    return check_schedule(schedule);
+}
+
+// The launch description of a planned batch whose workspace is `workspace`,
+// and its schedule (given, tuned for its size class, or the default).
+fsr_status finish_prepare(fsr_context* ctx, int32_t n, const fsr_params* params,
+                          const fsr_batch_schedule* schedule, const PlanTotals& plan, void* workspace,
+                          Prepared* prep) {
+    const int S = params->block + 2 * params->border;
     prep->launch.descs = reinterpret_cast<const DevDesc*>(static_cast<char*>(workspace) + kCtrlBytes);
     prep->launch.counter = static_cast<unsigned*>(workspace);
-    prep->launch.total_blocks = plan->total_blocks;
+    prep->launch.total_blocks = plan.total_blocks;
     prep->launch.n_images = n;
     prep->launch.block = params->block;
     prep->launch.border = params->border;
@@ -157,16 +184,31 @@ fsr_status prepare(fsr_context* ctx, const fsr_image_desc* descs, int32_t n, con
     } else {
         BatchState& bs = context_batch(ctx);
         std::lock_guard<std::mutex> lock(context_mutex(ctx));
-        auto it = bs.tuned.find(size_class(*plan, *params));
+        auto it = bs.tuned.find(size_class(plan, *params));
         prep->schedule = it != bs.tuned.end() ? it->second : default_schedule();
     }
     prep->launch.chunk = prep->schedule.chunk;
     if (prep->schedule.chunk > 0) {
         int cus = 0;
-        if ((st = cu_count(ctx, &cus)) != FSR_OK) return st;
+        fsr_status st = cu_count(ctx, &cus);
+        if (st != FSR_OK) return st;
         prep->groups = (int64_t)cus * prep->schedule.groups_per_cu;
     }
     return FSR_OK;
+}
+
+// Everything common to eager launches, autotuning and graph capture.
+fsr_status prepare(fsr_context* ctx, const fsr_image_desc* descs, int32_t n, const fsr_params* params,
+                   const fsr_batch_schedule* schedule, void* workspace, size_t ws_bytes,
+                   BatchPlan* plan, Prepared* prep) {
+    fsr_status st = check_batch_params(ctx, params, schedule);
+    if (st != FSR_OK) return st;
+    if ((st = plan_batch(descs, n, params, plan)) != FSR_OK) return st;
+    if (!workspace && n > 0) return errorf(FSR_ERR_INVALID_ARG, "workspace is NULL");
+    if (ws_bytes < workspace_bytes_for(n))
+        return errorf(FSR_ERR_INVALID_ARG, "workspace of %zu bytes is smaller than the %zu needed",
+                      ws_bytes, workspace_bytes_for(n));
+    return finish_prepare(ctx, n, params, schedule, plan->totals, workspace, prep);
 }
 
 // Puts the descriptor table into the workspace, ordered on `stream`: up to
@@ -236,7 +278,7 @@ fsr_status batched_enqueue(fsr_context* ctx, const fsr_image_desc* descs, int32_
     Prepared prep;
     fsr_status st = prepare(ctx, descs, n, params, schedule, workspace, ws_bytes, &plan, &prep);
     if (st != FSR_OK) return st;
-    if (plan.total_blocks == 0) return FSR_OK;
+    if (plan.totals.total_blocks == 0) return FSR_OK;
     DeviceGuard g(context_device(ctx));
     if (g.error() != hipSuccess) return hip_fail(g.error(), "hipSetDevice");
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
@@ -282,6 +324,45 @@ fsr_status fsr_reconstruct_batched(fsr_context* ctx, const fsr_image_desc* descs
                            &context_batch_mutex(ctx));
 }
 
+fsr_status fsr_reconstruct_batched_noalloc(fsr_context* ctx, const fsr_image_desc* descs, int32_t n_images,
+                                           const fsr_params* params, const fsr_batch_schedule* schedule,
+                                           void* stream) {
+    // planned in fixed arrays: nothing is allocated on the host either
+    fsr_status st = check_batch_params(ctx, params, schedule);
+    if (st != FSR_OK) return st;
+    if (n_images > kStaticImages)
+        return errorf(FSR_ERR_INVALID_ARG, "at most %d images per call without allocation (got %d)",
+                      kStaticImages, n_images);
+    int64_t blocks[kStaticImages];
+    int32_t order[kStaticImages];
+    DevDesc table[kStaticImages];
+    if ((st = check_images(descs, n_images, params, blocks)) != FSR_OK) return st;
+    // queue order by a stable insertion sort (std::stable_sort may allocate)
+    const QueueOrder before{descs, blocks};
+    for (int32_t i = 0; i < n_images; ++i) {
+        int32_t j = i;
+        for (; j > 0 && before(i, order[j - 1]); --j) order[j] = order[j - 1];
+        order[j] = i;
+    }
+    PlanTotals tot;
+    if ((st = fill_table(descs, n_images, params, order, blocks, table, &tot)) != FSR_OK) return st;
+    void* ws = static_workspace(context_device(ctx));
+    if (!ws) return errorf(FSR_ERR_HIP, "the fixed workspace of device %d was not found", context_device(ctx));
+    Prepared prep;
+    if ((st = finish_prepare(ctx, n_images, params, schedule, tot, ws, &prep)) != FSR_OK) return st;
+    if (tot.total_blocks == 0) return FSR_OK;
+    // tables must exist already: building them would allocate
+    if ((st = context_tables(ctx, prep.launch.support, params->rho, &prep.launch.tab, false)) != FSR_OK)
+        return st;
+    DeviceGuard g(context_device(ctx));
+    if (g.error() != hipSuccess) return hip_fail(g.error(), "hipSetDevice");
+    const hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_write_descs(table, n_images,
+                                      reinterpret_cast<DevDesc*>(static_cast<char*>(ws) + kCtrlBytes), s);
+    if (e != hipSuccess) return hip_fail(e, "descriptor upload");
+    return launch_prepared(prep, s);
+}
+
 fsr_status fsr_batch_autotune(fsr_context* ctx, const fsr_image_desc* descs, int32_t n_images,
                               const fsr_params* params, void* workspace, size_t workspace_bytes,
                               void* stream, fsr_batch_schedule* best) {
@@ -300,7 +381,7 @@ fsr_status fsr_batch_autotune(fsr_context* ctx, const fsr_image_desc* descs, int
                             &plan, &prep);
     if (st != FSR_OK) return st;
     *best = default_schedule();
-    if (plan.total_blocks == 0) return FSR_OK;
+    if (plan.totals.total_blocks == 0) return FSR_OK;
     DeviceGuard g(context_device(ctx));
     if (g.error() != hipSuccess) return hip_fail(g.error(), "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
@@ -352,7 +433,7 @@ fsr_status fsr_batch_autotune(fsr_context* ctx, const fsr_image_desc* descs, int
     (void)hipEventDestroy(t1);
     if (st != FSR_OK) return st;
     std::lock_guard<std::mutex> lock(context_mutex(ctx));
-    context_batch(ctx).tuned[size_class(plan, *params)] = *best;
+    context_batch(ctx).tuned[size_class(plan.totals, *params)] = *best;
     return FSR_OK;
 }
 
@@ -385,7 +466,7 @@ fsr_status fsr_batch_graph_create(fsr_context* ctx, const fsr_image_desc* descs,
     gr->device = context_device(ctx);
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        if (plan.total_blocks > 0) st = launch_prepared(prep, cs);
+        if (plan.totals.total_blocks > 0) st = launch_prepared(prep, cs);
         hipError_t e2 = hipStreamEndCapture(cs, &gr->graph);
         if (st == FSR_OK && e2 != hipSuccess) st = hip_fail(e2, "hipStreamEndCapture");
     } else {

@@ -14,7 +14,38 @@
 #include "fsr_block_multi.h"
 #include "fsr_block_sg.h"
 
+#include <mutex>
+
 namespace fsr {
+
+// The fixed workspace of fsr_reconstruct_batched_noalloc (queue head, then
+// descriptors).  Host code never passes this name to a kernel: it stands for
+// a host-side shadow; the device address comes from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[kStaticWorkspaceBytes];
+
+namespace {
+constexpr int kMaxStaticDevices = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxStaticDevices] = {};
+}  // namespace
+
+hipError_t static_workspace_init(int device) {
+    if (device < 0 || device >= kMaxStaticDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (g_static_ptr[device]) return hipSuccess;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_static_ptr[device] = ptr;
+    return hipSuccess;
+}
+
+void* static_workspace(int device) {
+    if (device < 0 || device >= kMaxStaticDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    return g_static_ptr[device];
+}
 
 __global__ void fsr_queue_reset(unsigned* counter) {
     if (threadIdx.x == 0) *counter = 0u;
