@@ -49,19 +49,19 @@ def _load():
         lib.fsro_freq_weight.argtypes = [c_int, dp]
         lib.fsro_dft2_real.argtypes = [c_int, dp, dp, dp]
         lib.fsro_block.argtypes = [c_int, c_int, c_double, c_double, c_int, dp, u8p,
-                                   dp, dp, dp, dp, u16p, dp]
+                                   dp, dp, dp, dp, u16p, dp, dp]
         lib.fsro_block.restype = c_int
         lib.fsro_model_pixel.argtypes = [c_int, dp, dp, c_int, c_int]
         lib.fsro_model_pixel.restype = c_double
         lib.fsro_reconstruct.argtypes = [dp, u8p, dp, c_int, c_int, c_long, c_int, c_int, c_int,
-                                         c_double, c_double, c_int, u16p, c_int]
+                                         c_double, c_double, c_int, u16p, dp, c_int]
         lib.fsro_reconstruct.restype = c_long
         lib.fsro_reconstruct_blocks.argtypes = [dp, u8p, c_int, c_int, c_long, c_int, c_int,
                                                 c_int, c_double, c_double, c_int, i64p, c_long,
-                                                dp, u16p, dp, c_int]
+                                                dp, u16p, dp, dp, c_int]
         lib.fsro_reconstruct_blocks.restype = c_long
         lib.fsro_block_weighted.argtypes = [c_int, c_int, c_double, c_int, dp, dp,
-                                            dp, dp, dp, dp, u16p, dp]
+                                            dp, dp, dp, dp, u16p, dp, dp]
         lib.fsro_block_weighted.restype = c_int
         lib.fsro_reconstruct_reuse.argtypes = [dp, u8p, dp, c_int, c_int, c_long, c_int, c_int,
                                                c_int, c_double, c_double, c_double, c_int, u16p]
@@ -132,19 +132,23 @@ def block(ft: np.ndarray, known: np.ndarray, iters: int, rho: float, gamma: floa
 
     Returns a dict with the final model ``G`` and residual ``R`` (complex
     S x S), the per-iteration picks ``idx`` (u*S + v), the projection
-    coefficients ``p`` (complex) and ``empty`` (no known pixel)."""
+    coefficients ``p`` (complex), the winning objectives ``obj`` and their
+    relative separations ``sep`` from the next objective (the winner's
+    exactly tied conjugate passed over), and ``empty`` (no known pixel)."""
     ft = _f64(ft)
     k = _u8(known)
     S = ft.shape[0]
     Gr, Gi, Rr, Ri = (np.empty((S, S)) for _ in range(4))
     idx = np.empty(max(iters, 1), np.uint16)
     p = np.empty(2 * max(iters, 1))
+    sep = np.empty(2 * max(iters, 1))
     D = ctypes.c_double
     empty = _load().fsro_block(S, iters, rho, gamma, int(tie_larger), _p(ft, D),
                                _p(k, ctypes.c_uint8), _p(Gr, D), _p(Gi, D), _p(Rr, D),
-                               _p(Ri, D), _p(idx, ctypes.c_uint16), _p(p, D))
+                               _p(Ri, D), _p(idx, ctypes.c_uint16), _p(p, D), _p(sep, D))
     return {"G": Gr + 1j * Gi, "R": Rr + 1j * Ri, "Gr": Gr, "Gi": Gi, "Rr": Rr, "Ri": Ri,
             "idx": idx[:iters].copy(), "p": (p[0::2] + 1j * p[1::2])[:iters],
+            "obj": sep[0::2][:iters].copy(), "sep": sep[1::2][:iters].copy(),
             "empty": bool(empty)}
 
 
@@ -161,7 +165,7 @@ def block_weighted(ft: np.ndarray, w: np.ndarray, iters: int, gamma: float,
     D = ctypes.c_double
     empty = _load().fsro_block_weighted(S, iters, gamma, int(tie_larger), _p(ft, D), _p(w, D),
                                         _p(Gr, D), _p(Gi, D), _p(Rr, D), _p(Ri, D),
-                                        _p(idx, ctypes.c_uint16), _p(p, D))
+                                        _p(idx, ctypes.c_uint16), _p(p, D), None)
     return {"G": Gr + 1j * Gi, "R": Rr + 1j * Ri, "Gr": Gr, "Gi": Gi, "Rr": Rr, "Ri": Ri,
             "idx": idx[:iters].copy(), "p": (p[0::2] + 1j * p[1::2])[:iters],
             "empty": bool(empty)}
@@ -175,9 +179,12 @@ def model_pixel(G: np.ndarray, m: int, n: int) -> float:
 
 def reconstruct(image: np.ndarray, mask: np.ndarray, iters: int, block_size: int = 4,
                 border: int = 14, rho: float = 0.7, gamma: float = 0.5,
-                tie_larger: bool = False, log: bool = False, threads: int = 0):
+                tie_larger: bool = False, log: bool = False, threads: int = 0,
+                separations: bool = False):
     """Whole-image FP64 reconstruction.  Returns ``(out, log_idx, n_empty)``;
-    ``log_idx`` is an (N, I) uint16 array when ``log`` is set, else None."""
+    ``log_idx`` is an (N, I) uint16 array when ``log`` is set, else None.
+    With ``separations`` a fourth item holds the (N, I) winning objectives
+    and the (N, I) relative separations of each pick (see :func:`block`)."""
     img = _f64(image)
     m = _u8(mask)
     H, W = img.shape
@@ -185,12 +192,15 @@ def reconstruct(image: np.ndarray, mask: np.ndarray, iters: int, block_size: int
     N = (-(-H // B)) * (-(-W // B))
     out = np.empty_like(img)
     lg = np.empty((N, max(iters, 1)), np.uint16) if log else None
+    ls = np.empty((N, max(iters, 1), 2)) if separations else None
     n_empty = _load().fsro_reconstruct(_p(img, ctypes.c_double), _p(m, ctypes.c_uint8),
                                        _p(out, ctypes.c_double), H, W, W, B, border, iters,
                                        rho, gamma, int(tie_larger), _p(lg, ctypes.c_uint16),
-                                       threads)
+                                       _p(ls, ctypes.c_double), threads)
     if lg is not None:
         lg = lg[:, :iters]
+    if separations:
+        return out, lg, int(n_empty), (ls[:, :iters, 0].copy(), ls[:, :iters, 1].copy())
     return out, lg, int(n_empty)
 
 
@@ -212,7 +222,7 @@ def reconstruct_blocks(image: np.ndarray, mask: np.ndarray, block_ids, iters: in
     n_empty = _load().fsro_reconstruct_blocks(
         _p(img, ctypes.c_double), _p(m, ctypes.c_uint8), H, W, W, B, border, iters, rho, gamma,
         int(tie_larger), _p(ids, ctypes.c_int64), n, _p(tg, ctypes.c_double),
-        _p(lg, ctypes.c_uint16), _p(lp, ctypes.c_double), threads)
+        _p(lg, ctypes.c_uint16), _p(lp, ctypes.c_double), None, threads)
     if lg is not None:
         lg = lg[:, :iters]
     p = None if lp is None else (lp[:, :iters, 0] + 1j * lp[:, :iters, 1])

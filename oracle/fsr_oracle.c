@@ -157,22 +157,27 @@ FSRO_API void fsro_dft2_real(int S, const double *x, double *Xr, double *Xi)
  *   Rr, Ri  S x S final weighted residual spectrum R_w
  *   log_idx I entries: selected bin u*S + v per iteration (0xFFFF if skipped)
  *   log_p   2I entries: projection coefficient p (re, im) per iteration
+ *   log_sep 2I entries per iteration: the winning objective w_f |R_w|^2 and
+ *           its relative separation (obj - next) / obj from the largest
+ *           objective of any other bin, where the winner's conjugate bin
+ *           (-u, -v) is passed over when its objective is exactly equal (a
+ *           tie Eq. 8 settles by the index rule); 0 when obj is 0
  * Returns 1 when the support holds no known pixel (no iteration ran), else 0.
  */
 FSRO_API int fsro_block_weighted(int S, int iters, double gamma, int tie_larger,
                                  const double *ft, const double *w,
                                  double *Gr_out, double *Gi_out, double *Rr_out, double *Ri_out,
-                                 uint16_t *log_idx, double *log_p);
+                                 uint16_t *log_idx, double *log_p, double *log_sep);
 
 FSRO_API int fsro_block(int S, int iters, double rho, double gamma, int tie_larger,
                         const double *ft, const uint8_t *known,
                         double *Gr_out, double *Gi_out, double *Rr_out, double *Ri_out,
-                        uint16_t *log_idx, double *log_p)
+                        uint16_t *log_idx, double *log_p, double *log_sep)
 {
     double *w = malloc(sizeof(double) * S * S);
     fsro_spatial_weight(S, rho, known, w);                /* O2 */
     int empty = fsro_block_weighted(S, iters, gamma, tie_larger, ft, w, Gr_out, Gi_out,
-                                    Rr_out, Ri_out, log_idx, log_p);
+                                    Rr_out, Ri_out, log_idx, log_p, log_sep);
     free(w);
     return empty;
 }
@@ -186,7 +191,7 @@ FSRO_API int fsro_block(int S, int iters, double rho, double gamma, int tie_larg
 FSRO_API int fsro_block_weighted(int S, int iters, double gamma, int tie_larger,
                                  const double *ft, const double *w,
                                  double *Gr_out, double *Gi_out, double *Rr_out, double *Ri_out,
-                                 uint16_t *log_idx, double *log_p)
+                                 uint16_t *log_idx, double *log_p, double *log_sep)
 {
     const int n2 = S * S;
     double *x = malloc(sizeof(double) * n2);
@@ -206,6 +211,7 @@ FSRO_API int fsro_block_weighted(int S, int iters, double gamma, int tie_larger,
         if (empty) {
             if (log_idx) log_idx[it] = 0xFFFF;
             if (log_p) { log_p[2 * it] = 0.0; log_p[2 * it + 1] = 0.0; }
+            if (log_sep) { log_sep[2 * it] = 0.0; log_sep[2 * it + 1] = 0.0; }
             continue;
         }
         /* (u,v) = argmax_{k,l} w_f |R_w|^2 (Eq. 8), scanned in linear order */
@@ -219,6 +225,20 @@ FSRO_API int fsro_block_weighted(int S, int iters, double gamma, int tie_larger,
             }
         }
         const int u = best / S, v = best % S;
+        if (log_sep) {
+            /* the largest objective of the other bins, the conjugate of the
+             * winner left out when it ties exactly */
+            const int conj = ((S - u) % S) * S + (S - v) % S;
+            double next = 0.0;
+            for (int b = 0; b < n2; ++b) {
+                if (b == best) continue;
+                const double ob = wf[b] * (Rr[b] * Rr[b] + Ri[b] * Ri[b]);
+                if (b == conj && ob == best_obj) continue;
+                if (ob > next) next = ob;
+            }
+            log_sep[2 * it] = best_obj;
+            log_sep[2 * it + 1] = best_obj > 0.0 ? (best_obj - next) / best_obj : 0.0;
+        }
         const double p_re = Rr[best] / w00, p_im = Ri[best] / w00;  /* Eq. 10 */
         Gr[best] += gamma * p_re * (double)n2;                      /* Eq. 11 */
         Gi[best] += gamma * p_im * (double)n2;
@@ -279,7 +299,8 @@ static void gather_support(const double *img, const uint8_t *mask, int H, int W,
  * (row-major B x B; entries of out-of-image pixels are left untouched). */
 static int reconstruct_one(const double *img, const uint8_t *mask, int H, int W, long stride,
                            int B, int L, int iters, double rho, double gamma, int tie_larger,
-                           long block_id, double *out_target, uint16_t *log_idx, double *log_p)
+                           long block_id, double *out_target, uint16_t *log_idx, double *log_p,
+                           double *log_sep)
 {
     const int S = B + 2 * L, n2 = S * S;
     const int nbx = (W + B - 1) / B;
@@ -289,7 +310,7 @@ static int reconstruct_one(const double *img, const uint8_t *mask, int H, int W,
     double *Gr = malloc(sizeof(double) * n2), *Gi = malloc(sizeof(double) * n2);
     gather_support(img, mask, H, W, stride, B, L, by, bx, ft, known);
     int empty = fsro_block(S, iters, rho, gamma, tie_larger, ft, known, Gr, Gi,
-                           NULL, NULL, log_idx, log_p);
+                           NULL, NULL, log_idx, log_p, log_sep);
     for (int i = 0; i < B; ++i)
         for (int j = 0; j < B; ++j) {
             int m = L + i, n = L + j;
@@ -308,12 +329,14 @@ static int reconstruct_one(const double *img, const uint8_t *mask, int H, int W,
  *   img, mask  H x W, row stride `stride` elements; mask != 0 means known
  *   out        H x W, row stride `stride`; every pixel is written
  *   log_idx    optional, N x I (N = ceil(H/B) * ceil(W/B), block-major)
+ *   log_sep    optional, N x I x 2: winning objective and its separation
+ *              (see fsro_block_weighted)
  * Returns the number of blocks whose support held no known pixel.
  */
 FSRO_API long fsro_reconstruct(const double *img, const uint8_t *mask, double *out,
                                int H, int W, long stride, int B, int L, int iters,
                                double rho, double gamma, int tie_larger,
-                               uint16_t *log_idx, int threads)
+                               uint16_t *log_idx, double *log_sep, int threads)
 {
     const int nby = (H + B - 1) / B, nbx = (W + B - 1) / B;
     const long N = (long)nby * nbx;
@@ -327,7 +350,7 @@ FSRO_API long fsro_reconstruct(const double *img, const uint8_t *mask, double *o
         double *t = (B * B <= 32 * 32) ? tgt : malloc(sizeof(double) * B * B);
         empty += reconstruct_one(img, mask, H, W, stride, B, L, iters, rho, gamma, tie_larger,
                                  b, t, log_idx ? log_idx + b * (long)iters : NULL,
-                                 NULL);
+                                 NULL, log_sep ? log_sep + 2 * b * (long)iters : NULL);
         const int by = (int)(b / nbx), bx = (int)(b % nbx);
         for (int i = 0; i < B; ++i)
             for (int j = 0; j < B; ++j) {
@@ -346,13 +369,15 @@ FSRO_API long fsro_reconstruct(const double *img, const uint8_t *mask, double *o
  *               entries are set to NaN)
  *   log_idx     optional, n x I
  *   log_p       optional, n x I x 2
+ *   log_sep     optional, n x I x 2 (see fsro_block_weighted)
  * Returns the number of listed blocks whose support held no known pixel.
  */
 FSRO_API long fsro_reconstruct_blocks(const double *img, const uint8_t *mask,
                                       int H, int W, long stride, int B, int L, int iters,
                                       double rho, double gamma, int tie_larger,
                                       const int64_t *block_ids, long n, double *out_targets,
-                                      uint16_t *log_idx, double *log_p, int threads)
+                                      uint16_t *log_idx, double *log_p, double *log_sep,
+                                      int threads)
 {
     long empty = 0;
 #ifdef _OPENMP
@@ -365,7 +390,8 @@ FSRO_API long fsro_reconstruct_blocks(const double *img, const uint8_t *mask,
         empty += reconstruct_one(img, mask, H, W, stride, B, L, iters, rho, gamma, tie_larger,
                                  (long)block_ids[i], t,
                                  log_idx ? log_idx + i * (long)iters : NULL,
-                                 log_p ? log_p + 2 * i * (long)iters : NULL);
+                                 log_p ? log_p + 2 * i * (long)iters : NULL,
+                                 log_sep ? log_sep + 2 * i * (long)iters : NULL);
     }
     return empty;
 }
@@ -405,7 +431,7 @@ static int reuse_block(const double *img, const uint8_t *mask, const double *src
             w[i] = k ? rp[i] : reused ? delta * rp[i] : 0.0;
         }
     const int empty = fsro_block_weighted(S, iters, gamma, tie_larger, ft, w, Gr, Gi, NULL, NULL,
-                                          log_idx, NULL);
+                                          log_idx, NULL, NULL);
     for (int i = 0; i < B; ++i)                           /* O8 on the target */
         for (int j = 0; j < B; ++j) {
             const int y = by * B + i, x = bx * B + j, m = L + i, n = L + j;

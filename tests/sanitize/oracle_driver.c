@@ -10,11 +10,11 @@
 
 long fsro_reconstruct(const double *img, const uint8_t *mask, double *out, int H, int W, long stride,
                       int B, int L, int iters, double rho, double gamma, int tie_larger,
-                      uint16_t *log_idx, int threads);
+                      uint16_t *log_idx, double *log_sep, int threads);
 long fsro_reconstruct_blocks(const double *img, const uint8_t *mask, int H, int W, long stride, int B,
                              int L, int iters, double rho, double gamma, int tie_larger,
                              const int64_t *block_ids, long n, double *out_targets, uint16_t *log_idx,
-                             double *log_p, int threads);
+                             double *log_p, double *log_sep, int threads);
 long fsro_reconstruct_reuse(const double *img, const uint8_t *mask, double *out, int H, int W,
                             long stride, int B, int L, int iters, double rho, double gamma, double delta,
                             int tie_larger, uint16_t *log_idx);
@@ -30,16 +30,17 @@ static int run(int H, int W, long stride, int B, int L, int iters)
     /* the log serves the whole image (nb blocks) and the two listed blocks */
     uint16_t *log = malloc(sizeof(uint16_t) * (nb > 2 ? nb : 2) * (iters > 0 ? iters : 1));
     double *tg = malloc(sizeof(double) * 2 * B * B), *lp = malloc(sizeof(double) * 2 * 2 * (iters > 0 ? iters : 1));
+    double *ls = malloc(sizeof(double) * 2 * (nb > 2 ? nb : 2) * (iters > 0 ? iters : 1));
     for (long i = 0; i < (long)H * stride; ++i) {
         img[i] = (double)(next() % 256);
         mask[i] = (uint8_t)(next() % 4 == 0);
     }
-    long e = fsro_reconstruct(img, mask, out, H, W, stride, B, L, iters, 0.7, 0.5, 0, log, 2);
+    long e = fsro_reconstruct(img, mask, out, H, W, stride, B, L, iters, 0.7, 0.5, 0, log, ls, 2);
     e += fsro_reconstruct_reuse(img, mask, out, H, W, stride, B, L, iters, 0.7, 0.5, 0.5, 0, log);
     int64_t ids[2] = {0, nb - 1};
-    e += fsro_reconstruct_blocks(img, mask, H, W, stride, B, L, iters, 0.7, 0.5, 0, ids, 2, tg, log, lp, 2);
+    e += fsro_reconstruct_blocks(img, mask, H, W, stride, B, L, iters, 0.7, 0.5, 0, ids, 2, tg, log, lp, ls, 2);
     printf("%dx%d stride %ld B=%d L=%d I=%d: %ld empty\n", H, W, stride, B, L, iters, e);
-    free(img); free(out); free(mask); free(log); free(tg); free(lp);
+    free(img); free(out); free(mask); free(log); free(tg); free(lp); free(ls);
     return 0;
 }
 

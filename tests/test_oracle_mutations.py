@@ -35,6 +35,8 @@ MUTANTS = {
                                   "const double p_re = Rr[best] / (2.0 * w00), p_im = Ri[best] / (2.0 * w00);"),
     "objective_without_freq_weight": ("double obj = wf[b] * (Rr[b] * Rr[b] + Ri[b] * Ri[b]);",
                                       "double obj = (Rr[b] * Rr[b] + Ri[b] * Ri[b]);"),
+    "separation_keeps_tied_conjugate": ("if (b == conj && ob == best_obj) continue;", ""),
+    "separation_from_the_smallest": ("if (ob > next) next = ob;", "if (ob < next || next == 0.0) next = ob;"),
     "objective_rounded_to_float32": ("double obj = wf[b] * (Rr[b] * Rr[b] + Ri[b] * Ri[b]);",
                                      "double obj = (float)(wf[b] * (Rr[b] * Rr[b] + Ri[b] * Ri[b]));"),
 }
@@ -58,6 +60,8 @@ PIN_CALLS = [
     pins.test_known_pixels_copied_bitwise,
     pins.test_zero_iterations_gives_zero_model,
     pins.test_fp64_decision_resolves_sub_float32_differences,
+    pins.test_separation_of_the_first_pick_closed_form,
+    lambda o: pins.test_separation_log_matches_the_residual(o, 16),
 ]
 
 

@@ -420,3 +420,61 @@ def test_fp64_decision_resolves_sub_float32_differences(oracle_lib):
         f, _, _ = objectives(alpha)
         r = oracle_lib.block(f, known, 1, 1.0, 0.5)
         assert int(r["idx"][0]) == expect, (alpha, int(r["idx"][0]))
+
+
+# ---------------------------------------------------------------- decision separations
+def np_separation(obj, best, S):
+    """Relative separation of the winner from the largest objective of any
+    other bin, the winner's conjugate passed over when it ties exactly."""
+    o = np.asarray(obj, np.float64).ravel().copy()
+    k, l = divmod(int(best), S)
+    conj = ((S - k) % S) * S + (S - l) % S
+    top = o[best]
+    o[best] = -1.0
+    if conj != best and o[conj] == top:
+        o[conj] = -1.0
+    nxt = max(float(o.max()), 0.0)
+    return (top - nxt) / top if top > 0 else 0.0
+
+
+def test_separation_of_the_first_pick_closed_form(oracle_lib):
+    """All pixels known and rho = 1: R(0) = DFT2(f) (numpy's FFT), so the first
+    pick's objective w_f |F|^2 and its separation follow in closed form.  With
+    the mean removed the winner is not DC; f is real, so the winner's
+    conjugate ties it exactly and the separation is measured to the third
+    largest objective, not 0."""
+    S = 8
+    rng = np.random.default_rng(15)
+    f = rng.uniform(0, 255, (S, S))
+    f -= f.mean()
+    known = np.ones((S, S), np.uint8)
+    obj = np_freq_weight(S) * np.abs(np.fft.fft2(f)) ** 2
+    r = oracle_lib.block(f, known, 1, 1.0, 0.5)
+    best = int(r["idx"][0])
+    order = np.argsort(obj.ravel())[::-1]
+    assert best == min(order[0], order[1]) and mirror(order[0], S) == order[1]
+    third = obj.ravel()[order[2]]
+    assert r["obj"][0] == pytest.approx(obj.ravel()[best], rel=1e-12)
+    assert r["sep"][0] == pytest.approx((obj.ravel()[best] - third) / obj.ravel()[best], rel=1e-9)
+    assert r["sep"][0] > 0.0
+
+
+@pytest.mark.parametrize("S", [8, 16, 32])
+def test_separation_log_matches_the_residual(oracle_lib, S):
+    """At every iteration the logged objective and separation are those of the
+    residual R(v) the iteration starts from (the oracle's own, pinned by the
+    residual identity), recomputed with numpy."""
+    I = 8
+    ft, known = random_support(S, 31 + S)
+    full = oracle_lib.block(ft, known, I, 0.7, 0.5)
+    wf = np_freq_weight(S)
+    for v in range(I):
+        R = oracle_lib.block(ft, known, v, 0.7, 0.5)["R"] if v else None
+        if R is None:
+            x = ft * np_weight(known, 0.7)
+            R = np.fft.fft2(x)
+        obj = wf * np.abs(R) ** 2
+        best = int(full["idx"][v])
+        assert obj.ravel()[best] == pytest.approx(obj.max(), rel=1e-12)
+        assert full["obj"][v] == pytest.approx(obj.ravel()[best], rel=1e-10)
+        assert full["sep"][v] == pytest.approx(np_separation(obj, best, S), rel=1e-6, abs=1e-12)
