@@ -16,15 +16,16 @@ import synth
 
 @functools.lru_cache(maxsize=None)
 def oracle_frame(name: str):
-    """``(img32, mask, out, log)`` for the named workload: the float32 input
-    both sides receive, its mask, and the oracle's FP64 output frame and
-    (N, I) argmax log over every block."""
+    """``(img32, mask, out, log, obj, sep)`` for the named workload: the
+    float32 input both sides receive, its mask, and the oracle's FP64 output
+    frame, (N, I) argmax log, winning objectives and their separations over
+    every block."""
     w = synth.workload(name)
     img, mask = w.inputs()
     img32 = img.astype(np.float32)
-    out, log, _ = oracle.reconstruct(img32.astype(np.float64), mask, w.iterations,
-                                     block_size=w.block, border=w.border, rho=w.rho,
-                                     gamma=w.gamma, log=True)
-    for a in (img32, mask, out, log):
+    out, log, _, (obj, sep) = oracle.reconstruct(img32.astype(np.float64), mask, w.iterations,
+                                                 block_size=w.block, border=w.border, rho=w.rho,
+                                                 gamma=w.gamma, log=True, separations=True)
+    for a in (img32, mask, out, log, obj, sep):
         a.setflags(write=False)
-    return img32, mask, out, log
+    return img32, mask, out, log, obj, sep

@@ -5,7 +5,8 @@ products with FP32 accumulation, every operand split into three bf16 terms
 (hi + mid + lo); the rest of the block routine is the FP32 one.  The same
 acceptance bar as the FP32 path applies, against the same FP64 oracle: known
 pixels bitwise, |gpu - oracle| <= 1 code value on >= 99.9 % of the unknown
-pixels, PSNR gap <= 0.05 dB, argmax agreement >= 99 %.  Each case prints its
+pixels, PSNR gap <= 0.05 dB, argmax agreement >= 99 %, and all but 1e-5 of
+the decisions of the blocks' resolvable prefixes (tests/decisions.py).  Each case prints its
 error figures next to those of the FP32 FFT path on the same input, so the
 error of each transform is stated per result.
 """
@@ -14,6 +15,7 @@ import pytest
 
 import oracle
 import synth
+from tests.decisions import PREFIX_AGREE, decision_report
 from tests.frames import oracle_frame
 from synth.metrics import parity_report
 
@@ -60,16 +62,24 @@ def check(rep, name):
         assert rep["argmax_agree"] >= ARGMAX
 
 
+def check_decisions(gl, ol, obj, sep, name):
+    dec = decision_report(gl, ol, obj, sep)
+    print(f"[decisions] {name}: {dec}", flush=True)
+    assert dec["prefix_agree"] >= PREFIX_AGREE, dec
+
+
 def test_small64_against_oracle(ctx):
     announce("split-bf16 DFT: small64 64x64 quarter I=100, every pixel")
     w = synth.workload("small64")
     img, mask = w.inputs()
     img32 = img.astype(np.float32)
-    o, ol, _ = oracle.reconstruct(img32.astype(np.float64), mask, w.iterations, log=True)
+    o, ol, _, (obj, sep) = oracle.reconstruct(img32.astype(np.float64), mask, w.iterations, log=True,
+                                              separations=True)
     for dft, tag in ((fsr.FSR_DFT_FP32, "fp32"), (BF16, "split-bf16")):
         g, gl = run(ctx, img32, mask, params_of(w, dft))
         rep = parity_report(img32, mask, g, o, gl, ol)
         check(rep, f"small64 {tag}")
+        check_decisions(gl, ol, obj, sep, f"small64 {tag}")
 
 
 @pytest.mark.parametrize("name", ["fhd_quarter", "uhd_concealment"])
@@ -79,12 +89,13 @@ def test_full_frames_every_block(ctx, name):
     and every logged (block, iteration)."""
     announce(f"split-bf16 DFT: {name}, full frame, every block, beside the FP32 FFTs")
     w = synth.workload(name)
-    img32, mask, o, ol = oracle_frame(name)
+    img32, mask, o, ol, obj, sep = oracle_frame(name)
     for dft, tag in ((fsr.FSR_DFT_FP32, "fp32"), (BF16, "split-bf16")):
         g, gl = run(ctx, img32, mask, params_of(w, dft))
         assert np.array_equal(g[mask != 0], img32[mask != 0])
         assert np.all(np.isfinite(g))
         check(parity_report(img32, mask, g, o, gl, ol), f"{name} {tag} every block")
+        check_decisions(gl, ol, obj, sep, f"{name} {tag} every block")
 
 
 def test_edge_cases_against_oracle(ctx):
