@@ -12,6 +12,7 @@
 #include "fsr_batch_internal.h"
 #include "fsr_block.h"
 #include "fsr_block_multi.h"
+#include "fsr_block_s24.h"
 #include "fsr_block_sg.h"
 
 #include <mutex>
@@ -151,6 +152,8 @@ __device__ __forceinline__ void batch_block(const BatchLaunch& p, int64_t g, int
     if constexpr (S == kS)
         reconstruct_block<kDft, kArgmaxWave, kPersistent>(batch_job(p, g, img), p.block, p.border,
                                                           p.gamma, p.tab, lds);
+    else if constexpr (S == S24::S)
+        reconstruct_block_s24<kPersistent>(batch_job(p, g, img), p.block, p.border, p.gamma, p.tab, lds);
     else
         reconstruct_block_sg<S, kPersistent>(batch_job(p, g, img), p.block, p.border, p.gamma, p.tab, lds);
 }
@@ -158,6 +161,7 @@ __device__ __forceinline__ void batch_block(const BatchLaunch& p, int64_t g, int
 template <int S>
 constexpr int lds_floats_of() {
     if constexpr (S == kS) return kLdsFloats;
+    else if constexpr (S == S24::S) return S24::kLdsFloats;
     else return SgShape<S>::kLdsFloats;
 }
 
@@ -218,13 +222,13 @@ __global__ __launch_bounds__(64 * kWaves) void fsr_batched_s32(BatchLaunch p) {
 
 template <int kWaves, int S>
 __global__ __launch_bounds__(64 * kWaves) void fsr_batched_grid_sg(BatchLaunch p) {
-    __shared__ __align__(16) float lds[kWaves * SgShape<S>::kLdsFloats];
+    __shared__ __align__(16) float lds[kWaves * lds_floats_of<S>()];
     grid_body<kWaves, S, kDftFft32>(p, lds);
 }
 
 template <int kWaves, int S>
 __global__ __launch_bounds__(64 * kWaves) void fsr_batched_sg(BatchLaunch p) {
-    __shared__ __align__(16) float lds[kWaves * SgShape<S>::kLdsFloats];
+    __shared__ __align__(16) float lds[kWaves * lds_floats_of<S>()];
     queue_body<kWaves, S, kDftFft32>(p, lds);
 }
 

@@ -285,6 +285,10 @@ __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int
             xr[s] = fmaf(mu, wr[s], xr[s]);
             xi[s] = fmaf(mu, wi[s], xi[s]);
         }
+        // W itself, not gamma W / W[0,0]: a per-bin rounding of the table
+        // would not cancel against R_w where R_w is proportional to W (a
+        // support with one known pixel), and as R_w shrinks the error of the
+        // early iterations would take over the argmax
         float2* wtab = reinterpret_cast<float2*>(lds);
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
@@ -297,12 +301,15 @@ __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int
         float wf[16];
 #pragma unroll
         for (int s = 0; s < 16; ++s) wf[s] = global_ptr(tab.freq_w)[(2 * s + h) * kS + c];
-        // lane i of tw_re/tw_im holds t32[i & 31] for the target model's phases
+        // lane i of tw_re/tw_im holds t32[i & 31] for the target model's
+        // phases; ds_bpermute reads lane (address / 4) mod 64, so the byte
+        // address 4 q needs no reduction mod 32
         const int tw_re = __float_as_int(kTw.re[c]), tw_im = __float_as_int(kTw.im[c]);
-        // loop-invariant lane offsets: bpermute byte addresses of the target
-        // phases are 4 q, LDS byte offsets of W are 256 row + 8 column
-        const int tm4 = opaque(4 * tm), tn4 = opaque(4 * tn);
-        const int h256 = opaque(256 * h), c8 = opaque(8 * c);
+        // loop-invariant lane constants: the target pixel's (4 m, 4 n) packed
+        // for the phase's bpermute byte address 4 (u m + v n), and the LDS
+        // byte offset 256 h + 8 c of the lane's entry (h, c) in W
+        const int tmn4 = opaque((4 * tm) | ((4 * tn) << 16));
+        const int hc8 = opaque(256 * h + 8 * c);
         wave_sync();
 
         // the residual spectrum lives in two 16-wide vectors during the
@@ -369,7 +376,7 @@ __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int
             if (jb.log != nullptr && lane == 0) jb.log[it] = (uint16_t)idx;
 
             // model: g += gamma p exp(+j 2 pi (u m + v n) / S) on the target
-            const int q4 = mad_u24(v, tn4, mul_u24(u, tm4)) & 124;
+            const int q4 = dot2_u16(u | (v << 16), tmn4);
             const float er = __int_as_float(__builtin_amdgcn_ds_bpermute(q4, tw_re));
             const float ei = __int_as_float(__builtin_amdgcn_ds_bpermute(q4, tw_im));
             if constexpr (kDft == kDftSplitBf16) {
@@ -384,8 +391,10 @@ __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int
             }
 
             // residual: R_w[k,l] -= gamma p W[(k-u) mod S, (l-v) mod S]; slot s
-            // reads duplicated row (h - u) mod 32 + 2s at byte offset 512 s
-            const int woff = ((h256 - 256 * u) & 0x1F00) | ((c8 - 8 * v) & 0xF8);
+            // reads duplicated row h + 32 - u + 2s (rows 1 .. 63 of the
+            // table), column (c - v) mod 32: byte offset 256 (h + 32 - u) +
+            // 8 ((c - v) mod 32) + 512 s
+            const int woff = sub_low_byte(hc8 + (8192 - 256 * u), 8 * v);
             const float2* wrow = reinterpret_cast<const float2*>(
                 reinterpret_cast<const char*>(wtab) + woff);
 #pragma unroll

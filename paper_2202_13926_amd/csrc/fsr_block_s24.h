@@ -1,0 +1,354 @@
+// fsr_block_s24.h -- one support block of FSR on one wavefront at S = 24
+// with every lane busy (Sec. II; the paper sweeps S up to 32 in Sec. IV).
+//
+// Layout: lane = 8 a + b (a, b < 8), slot s = 3 i + j (i, j < 3); slot s of
+// lane (a, b) holds pixel, or bin, (a + 8 i, b + 8 j): the 576 bins fill
+// 64 lanes x 9 slots, where the generic layout of fsr_block_sg.h (one column
+// per lane) leaves 16 lanes idle at this size.
+//
+// Argmax ties (Eq. 8: equal objectives go to the smaller bin k S + l).  The
+// bin index 192 i + 24 a + 8 j + b does not order as (slot, lane), so the
+// key's tie code cannot be the slot alone.  The ties that occur exactly are
+// those between a bin and its conjugate (-k, -l), which R_w has while it is
+// Hermitian.  Each bin therefore carries a per-lane code: 15 - s when it is
+// the smaller bin of its conjugate pair (or its own conjugate), 6 - r when
+// it is the r-th larger-of-pair bin of its lane (a lane holds at most six
+// of either kind).  The smaller bin of a pair thus always has the larger
+// code; equal keys, which share a code, go to the lower lane, and within one
+// slot that is the smaller bin.  A key's code and lane give back its slot.
+//
+// DFT: both real tiles in one complex transform z = (f~ - mu) w + j s w
+// (s a power of two, as in the S = 32 kernel), by direct separable sums
+// against the table F[m][k] = exp(-j 2 pi m k / S) in LDS, then split into
+// the two exactly Hermitian spectra.
+//
+// LDS per wavefront: the DFT table (S^2 float2) and a scratch area (S^2
+// float2: the tile, then the first pass, then the spectrum) during the
+// transforms; during the iterations W with its first 16 rows and columns
+// repeated, 40 x 40 entries (entry (R, C) = W[R mod S][C mod S]), 12.5 KiB.
+// A lane's nine entries (r0 + 8 i, c0 + 8 j) of the shifted spectrum of
+// Eqs. 14-15 then lie at immediate offsets from one base, with r0 and c0
+// the lane's row and column shifted and wrapped once per iteration.  Rows
+// and columns duplicated in full (48 x 48 at a pitch of 52, 19.5 KiB) make
+// that base a uniform offset, but leave two wavefronts per SIMD instead of
+// three: measured on the 1080p frame at I = 100, 3.50 ms in full, 2.97 ms
+// with only the rows in full, 2.57 ms as here (the 48-lane layout of
+// fsr_block_sg.h: 3.27 ms).
+#pragma once
+
+#include "fsr_block.h"
+#include "fsr_block_sg.h"
+
+namespace fsr {
+
+struct S24 {
+    static constexpr int S = 24;
+    static constexpr int NS = 9;                  // slots per lane
+    static constexpr int kDup = 40;               // table rows and columns: 24 + 16 copies
+    static constexpr int kPitch = 40;             // W table pitch, float2
+    static constexpr int kTabFloats = 2 * S * S;  // DFT table, then scratch
+    static constexpr int kLdsFloats = 2 * kDup * kPitch;
+    static_assert(2 * kTabFloats <= kLdsFloats, "transforms fit under the W table");
+    static constexpr int kArgmaxPairs = 1024;     // 576 (key, lane) pairs, padded to 2^10
+};
+
+// Tie codes of this lane's bins (see above) and the slot of each code of a
+// larger-of-pair bin: nibble r of *lmap holds the slot whose code is 6 - r.
+__device__ __forceinline__ void s24_codes(int a, int b, uint32_t (&code)[S24::NS], uint32_t* lmap) {
+    constexpr int S = S24::S;
+    int r = 0;
+    uint32_t m = 0;
+#pragma unroll
+    for (int s = 0; s < S24::NS; ++s) {
+        const int k = a + 8 * (s / 3), l = b + 8 * (s % 3);
+        const int kc = k ? S - k : 0, lc = l ? S - l : 0;
+        const bool larger = k * S + l > kc * S + lc;
+        code[s] = larger ? (uint32_t)(6 - r) : (uint32_t)(15 - s);
+        m |= larger ? (uint32_t)s << (4 * r) : 0u;
+        r += larger ? 1 : 0;
+    }
+    *lmap = m;
+}
+
+// kPersistent as in the other block routines (the caller loops over blocks).
+// kArgmax: kArgmaxWave, or kArgmaxLds (every (key, lane) pair through a
+// shared-memory tree, argmax_lds holding S24::kArgmaxPairs pairs); both pick
+// the same bin.
+template <bool kPersistent = false, int kArgmax = kArgmaxWave>
+__device__ __forceinline__ void reconstruct_block_s24(const BlockJob& jb, int B, int L, float gamma,
+                                                      const BlockTables& tab_in, float* lds,
+                                                      uint2* argmax_lds = nullptr) {
+    constexpr int S = S24::S, NS = S24::NS, P = S24::kPitch;
+    const int lane = kPersistent ? opaque((int)(threadIdx.x & 63)) : (int)(threadIdx.x & 63);
+    BlockTables tab = tab_in;
+    if constexpr (kPersistent) {
+        tab.rho_pow = opaque_ptr(tab_in.rho_pow);
+        tab.freq_w = opaque_ptr(tab_in.freq_w);
+        tab.dft_sg = opaque_ptr(tab_in.dft_sg);
+    }
+    const int a = lane >> 3, b = lane & 7;
+    const int y0 = jb.by * B - L, x0 = jb.bx * B - L;
+    float2* ftab = reinterpret_cast<float2*>(lds);
+    float2* scr = reinterpret_cast<float2*>(lds + S24::kTabFloats);
+
+    // ---- DFT table into LDS (the same for every block)
+    {
+        const global_t<const uint64_t>* src = global_ptr(reinterpret_cast<const uint64_t*>(tab.dft_sg));
+        uint64_t* dst = reinterpret_cast<uint64_t*>(ftab);
+        for (int i = lane; i < S * S; i += 64) dst[i] = src[i];
+    }
+
+    // ---- gather and weighting: slot s holds pixel (a + 8 i, b + 8 j)
+    float xr[NS], wr[NS];
+    uint64_t any_known = 0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int m = a + 8 * (s / 3), n = b + 8 * (s % 3);
+        const int y = y0 + m, x = x0 + n;
+        const bool in = (unsigned)y < (unsigned)jb.height && (unsigned)x < (unsigned)jb.width;
+        const int64_t off = in ? (int64_t)y * jb.stride + x : 0;
+        const uint8_t kraw = jb.mask[off];
+        const float fraw = jb.image[off];
+        const float rp = global_ptr(tab.rho_pow)[m * S + n];
+        const uint8_t k = in ? kraw : (uint8_t)0;
+        any_known |= ballot(k != 0);
+        xr[s] = k ? fraw : 0.0f;
+        wr[s] = k ? rp : 0.0f;
+    }
+
+    // ---- target pixel owned by this lane (lanes 0 .. B*B-1; the other
+    // lanes model pixel (L, L) and discard it)
+    const bool owner = lane < B * B;
+    const int ti = owner ? lane / B : 0, tj = owner ? lane - (lane / B) * B : 0;
+    const int tm = L + ti, tn = L + tj;
+    float acc = 0.0f;
+    const int iters = jb.iterations;
+    wave_sync();   // DFT table written
+
+    if (any_known != 0) {
+        // ---- R_w = mu W + DFT2((f~ - mu) w), mu the weighted mean of the
+        // known support pixels, as in the other block routines
+        float sx = 0.0f, sw = 0.0f;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            sx = fmaf(xr[s], wr[s], sx);
+            sw += wr[s];
+        }
+        sx = wave_sum_f32(sx);
+        sw = wave_sum_f32(sw);
+        const float mu = sw > 0.0f ? sx / sw : 0.0f;
+        uint32_t amax = 0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            xr[s] = (xr[s] - mu) * wr[s];
+            amax = umax(amax, __float_as_uint(fabsf(xr[s])));
+        }
+        amax = wave_max_u32(amax);
+        // z = x + j sc w with sc the power of two at or below max |x| (exact)
+        const uint32_t sbits = amax & 0x7F800000u;
+        const float sc = sbits ? __uint_as_float(sbits) : 1.0f;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) scr[(a + 8 * (s / 3)) * S + b + 8 * (s % 3)] = make_float2(xr[s], wr[s] * sc);
+        wave_sync();
+
+        // pass 1 along m: C[k][n] = sum_m z[m][n] F[m][k], k = a + 8 i, n = b + 8 j
+        float c1r[NS], c1i[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) c1r[s] = c1i[s] = 0.0f;
+#pragma unroll 2
+        for (int m = 0; m < S; ++m) {
+            float2 z[3], f[3];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) z[j] = scr[m * S + b + 8 * j];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) f[i] = ftab[m * S + a + 8 * i];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const float2 zz = z[s % 3], ff = f[s / 3];
+                c1r[s] = fmaf(zz.x, ff.x, c1r[s]);
+                c1r[s] = fmaf(-zz.y, ff.y, c1r[s]);
+                c1i[s] = fmaf(zz.x, ff.y, c1i[s]);
+                c1i[s] = fmaf(zz.y, ff.x, c1i[s]);
+            }
+        }
+        wave_sync();   // every lane has read the tile
+#pragma unroll
+        for (int s = 0; s < NS; ++s) scr[(a + 8 * (s / 3)) * S + b + 8 * (s % 3)] = make_float2(c1r[s], c1i[s]);
+        wave_sync();
+        // pass 2 along n: Z[k][l] = sum_n C[k][n] F[n][l], l = b + 8 j
+        float zr[NS], zi[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) zr[s] = zi[s] = 0.0f;
+#pragma unroll 2
+        for (int n = 0; n < S; ++n) {
+            float2 cc[3], f[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) cc[i] = scr[(a + 8 * i) * S + n];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) f[j] = ftab[n * S + b + 8 * j];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const float2 c2 = cc[s / 3], ff = f[s % 3];
+                zr[s] = fmaf(c2.x, ff.x, zr[s]);
+                zr[s] = fmaf(-c2.y, ff.y, zr[s]);
+                zi[s] = fmaf(c2.x, ff.y, zi[s]);
+                zi[s] = fmaf(c2.y, ff.x, zi[s]);
+            }
+        }
+        wave_sync();   // every lane has read the first pass
+#pragma unroll
+        for (int s = 0; s < NS; ++s) scr[(a + 8 * (s / 3)) * S + b + 8 * (s % 3)] = make_float2(zr[s], zi[s]);
+        wave_sync();
+        // split Z = F2{x + j sc w} into X = (Z + conj Z[-k]) / 2 and
+        // W = (Z - conj Z[-k]) / (2 j sc): bins k and -k read the same pair
+        // of values in swapped roles, so both come out exactly Hermitian
+        const float h = 0.5f / sc;
+        float xi[NS], wi[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int k = a + 8 * (s / 3), l = b + 8 * (s % 3);
+            const int km = k ? S - k : 0, lm = l ? S - l : 0;
+            const float2 zm = scr[km * S + lm];
+            const float ar = zr[s], ai = zi[s];
+            xr[s] = 0.5f * (ar + zm.x);
+            xi[s] = 0.5f * (ai - zm.y);
+            wr[s] = (ai + zm.y) * h;
+            wi[s] = (zm.x - ar) * h;
+        }
+        if (amax == 0) {
+            // every known pixel equals mu: X is exactly 0 (no rounding of the
+            // w part may leak into it)
+#pragma unroll
+            for (int s = 0; s < NS; ++s) xr[s] = xi[s] = 0.0f;
+        }
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            xr[s] = fmaf(mu, wr[s], xr[s]);
+            xi[s] = fmaf(mu, wi[s], xi[s]);
+        }
+        const float w00 = readlane_f(wr[0], 0);
+        const float gi = w00 > 0.0f ? gamma / w00 : 0.0f;
+        float wf[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) wf[s] = global_ptr(tab.freq_w)[(a + 8 * (s / 3)) * S + b + 8 * (s % 3)];
+        // lane i of tw_re / tw_im holds F[1][i mod S], read before the W
+        // table overwrites the DFT table
+        const float2 tw = ftab[S + (lane % S)];
+        const int tw_re = __float_as_int(tw.x), tw_im = __float_as_int(tw.y);
+        uint32_t code[NS], lmap;
+        s24_codes(a, b, code, &lmap);
+        wave_sync();   // every lane has read the spectrum and the table
+        // W, rows and columns duplicated
+        float2* wtab = reinterpret_cast<float2*>(lds);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int k = a + 8 * (s / 3), l = b + 8 * (s % 3);
+            const float2 wv = make_float2(wr[s], wi[s]);
+            wtab[k * P + l] = wv;
+            if (l + S < S24::kDup) wtab[k * P + l + S] = wv;
+            if (k + S < S24::kDup) {
+                wtab[(k + S) * P + l] = wv;
+                if (l + S < S24::kDup) wtab[(k + S) * P + l + S] = wv;
+            }
+        }
+        // lane constants kept as computed here
+        const int a8p = opaque(8 * P * a), b8 = opaque(8 * b);
+        const int tmn = opaque(tm | (tn << 16));
+        const char* wbytes = reinterpret_cast<const char*>(wtab);
+        wave_sync();
+
+        for (int it = 0; it < iters; ++it) {
+            // objective (Eq. 16) as an argmax key: the float32 bits with the
+            // 4 low mantissa bits replaced by the bin's tie code
+            uint32_t key[NS];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const float e = fmaf(xr[s], xr[s], xi[s] * xi[s]);
+                key[s] = (__float_as_uint(e * wf[s]) & 0xFFFFFFF0u) | code[s];
+            }
+            uint32_t mx;
+            int ln;
+            if constexpr (kArgmax == kArgmaxWave) {
+                uint32_t lmax = 0;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) lmax = umax(lmax, key[s]);
+                mx = wave_max_u32(lmax);
+                ln = (int)__builtin_ctzll(ballot(lmax == mx));
+            } else {
+#pragma unroll
+                for (int s = 0; s < NS; ++s) argmax_lds[64 * s + lane] = make_uint2(key[s], (uint32_t)lane);
+#pragma unroll
+                for (int e = 64 * NS; e < S24::kArgmaxPairs; e += 64)
+                    argmax_lds[e + lane] = make_uint2(0u, 0xFFFFFFFFu);
+                wave_sync();
+#pragma unroll
+                for (int half = S24::kArgmaxPairs / 2; half >= 64; half >>= 1) {
+#pragma unroll
+                    for (int j = 0; j < half / 64; ++j) {
+                        const int e = lane + 64 * j;
+                        argmax_lds[e] = better_pair(argmax_lds[e], argmax_lds[e + half]);
+                    }
+                    wave_sync();
+                }
+#pragma unroll
+                for (int half = 32; half >= 1; half >>= 1) {
+                    if (lane < half) argmax_lds[lane] = better_pair(argmax_lds[lane], argmax_lds[lane + half]);
+                    wave_sync();
+                }
+                mx = (uint32_t)__builtin_amdgcn_readfirstlane((int)argmax_lds[0].x);
+                ln = __builtin_amdgcn_readfirstlane((int)argmax_lds[0].y);
+                wave_sync();   // the next iteration overwrites the pairs
+            }
+            // the winner's slot from its code
+            const int cw = (int)(mx & 15u);
+            const uint32_t lm = (uint32_t)__builtin_amdgcn_readlane((int)lmap, ln);
+            const int slot = cw >= 7 ? 15 - cw : (int)((lm >> (4 * (6 - cw))) & 15u);
+            const int u = (ln >> 3) + 8 * (slot / 3), v = (ln & 7) + 8 * (slot % 3);
+            const float pr = readlane_f(xr[slot], ln);
+            const float pim = readlane_f(xi[slot], ln);
+            const float cr = gi * pr, ci = gi * pim;    // gamma * p (Eqs. 10-11)
+            if (jb.log != nullptr && lane == 0) jb.log[it] = (uint16_t)(u * S + v);
+
+            // model: g += gamma p exp(+j 2 pi (u m + v n) / S) on the target
+            const int q4 = 4 * mod_small<S>(dot2_u16(u | (v << 16), tmn));
+            const float er = __int_as_float(__builtin_amdgcn_ds_bpermute(q4, tw_re));
+            const float ei = __int_as_float(__builtin_amdgcn_ds_bpermute(q4, tw_im));
+            acc = fmaf(cr, er, acc);
+            acc = fmaf(ci, ei, acc);
+
+            // residual (Eqs. 12, 14-15): bin (k, l) = (a + 8 i, b + 8 j) reads
+            // W[(k - u) mod S][(l - v) mod S], table entry (r0 + 8 i, c0 + 8 j)
+            // with r0 = (a - u) mod S and c0 = (b - v) mod S (below 40), so the
+            // slot's entry is an immediate offset from the lane's base.  The
+            // wrap of 8 P (a - u) into [0, 8 P S) is a minimum of unsigned
+            // values: the difference itself when a >= u, else it plus 8 P S
+            const int r = a8p - 8 * P * u, cc = b8 - 8 * v;
+            const int addr = (int)umin((uint32_t)r, (uint32_t)(r + 8 * P * S)) +
+                             (int)umin((uint32_t)cc, (uint32_t)(cc + 8 * S));
+            const float2* wrow = reinterpret_cast<const float2*>(wbytes + addr);
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const float2 w = wrow[8 * P * (s / 3) + 8 * (s % 3)];
+                xr[s] = fmaf(-cr, w.x, xr[s]);
+                xr[s] = fmaf(ci, w.y, xr[s]);
+                xi[s] = fmaf(-cr, w.y, xi[s]);
+                xi[s] = fmaf(-ci, w.x, xi[s]);
+            }
+        }
+        wave_sync();   // the LDS is reused by the next block of a persistent wave
+    } else if (jb.log != nullptr) {
+        for (int it = lane; it < iters; it += 64) jb.log[it] = (uint16_t)0xFFFF;
+    }
+
+    // ---- compose (Sec. II): known pixels copied, unknown pixels Re g
+    if (owner) {
+        const int y = jb.by * B + ti, xx = jb.bx * B + tj;
+        if (y < jb.height && xx < jb.width) {
+            const int64_t off = (int64_t)y * jb.stride + xx;
+            const uint8_t k = jb.mask[off];
+            jb.out[off] = k ? jb.image[off] : acc;
+        }
+    }
+}
+
+}  // namespace fsr

@@ -255,7 +255,11 @@ __device__ __forceinline__ void reconstruct_block_sg(const BlockJob& jb, int B, 
         // lane constants kept as computed here (the compiler would otherwise
         // re-derive them inside the loop)
         const int lbase = opaque(8 * (h * P + (kFullDup ? c : 0)));   // entry (h, c), or row h
-        const int tm4 = opaque(4 * tm), tn4 = opaque(4 * tn);
+        // the target pixel's (m, n) packed for the phase index u m + v n,
+        // scaled by 4 (a bpermute byte address) where no reduction follows
+        constexpr int kQs = 64 % S == 0 ? 4 : 1;
+        const int tmn = opaque((kQs * tm) | ((kQs * tn) << 16));
+        const int c8 = opaque(8 * c);
         const char* wbytes = reinterpret_cast<const char*>(wtab);
         wave_sync();
 
@@ -327,11 +331,13 @@ __device__ __forceinline__ void reconstruct_block_sg(const BlockJob& jb, int B, 
             const float cr = gi * pr, ci = gi * pim;    // gamma * p (Eqs. 10-11)
             if (jb.log != nullptr && lane == 0) jb.log[it] = (uint16_t)idx;
 
-            // model: g += gamma p exp(+j 2 pi (u m + v n) / S) on the target;
-            // the phase index on the 24-bit multiplier
+            // model: g += gamma p exp(+j 2 pi (u m + v n) / S) on the target.
+            // Lane i holds F[1][i mod S]; ds_bpermute reads
+            // lane (address / 4) mod 64, so for S dividing 64 the byte
+            // address 4 q needs no reduction mod S
             int q4;
-            if constexpr ((S & (S - 1)) == 0) q4 = mad_u24(u, tm4, mul_u24(v, tn4)) & (4 * S - 1);
-            else q4 = 4 * mod_small<S>(mad_u24(u, tm, mul_u24(v, tn)));
+            if constexpr (64 % S == 0) q4 = dot2_u16(u | (v << 16), tmn);
+            else q4 = 4 * mod_small<S>(dot2_u16(u | (v << 16), tmn));
             const float er = __int_as_float(__builtin_amdgcn_ds_bpermute(q4, tw_re));
             const float ei = __int_as_float(__builtin_amdgcn_ds_bpermute(q4, tw_im));
             acc = fmaf(cr, er, acc);
@@ -344,6 +350,11 @@ __device__ __forceinline__ void reconstruct_block_sg(const BlockJob& jb, int B, 
             const float2* wrow;
             if constexpr (kFullDup) {
                 wrow = reinterpret_cast<const float2*>(wbytes + lbase + 8 * ((S - u) * P + (S - v)));
+            } else if constexpr ((S & (S - 1)) == 0) {
+                // the row offset is a multiple of 8 S, the wrapped column
+                // offset 8 ((c - v) mod S) lies below it
+                const int col8 = (c8 - 8 * v) & (8 * S - 8);
+                wrow = reinterpret_cast<const float2*>(wbytes + ((lbase + 8 * (S - u) * P) | col8));
             } else {
                 int col = c - v;
                 col += col < 0 ? S : 0;

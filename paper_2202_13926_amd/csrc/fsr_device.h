@@ -187,6 +187,7 @@ __device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
 }
 
 __device__ __forceinline__ uint32_t umax(uint32_t a, uint32_t b) { return a > b ? a : b; }
+__device__ __forceinline__ uint32_t umin(uint32_t a, uint32_t b) { return a < b ? a : b; }
 
 // Maximum of v over the 64 lanes, returned as a wave-uniform value.
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
@@ -237,6 +238,27 @@ __device__ __forceinline__ int mul_u24(int a, int b) {
     int r;
     asm("v_mul_u32_u24 %0, %1, %2" : "=v"(r) : "s"(a), "v"(b));
     return r;
+}
+
+// u a + v b in one instruction (packed 16-bit dot product): uv = u | v << 16
+// is wave-uniform, ab = a | b << 16 a lane constant, all four below 2^16 and
+// the result below 2^32.
+__device__ __forceinline__ int dot2_u16(int uv, int ab) {
+    int r;
+    asm("v_dot2_u32_u16 %0, %1, %2, 0" : "=v"(r) : "s"(uv), "v"(ab));
+    return r;
+}
+
+// y with its lowest byte replaced by (y - b) mod 256 and the other bytes
+// kept (a sub-dword write): with y's low byte 8 c and b = 8 v, the cyclic
+// column (c - v) mod 32 of a 32-entry row of 8-byte elements in one
+// instruction.  b is wave-uniform.
+__device__ __forceinline__ int sub_low_byte(int y, int b) {
+    asm("v_sub_u32_sdwa %0, %0, %1 dst_sel:BYTE_0 dst_unused:UNUSED_PRESERVE src0_sel:DWORD "
+        "src1_sel:DWORD"
+        : "+v"(y)
+        : "s"(b));
+    return y;
 }
 
 // Orders this wavefront's LDS accesses (its own LDS region only): a fence at

@@ -1,9 +1,10 @@
 // fsr_plain_sg.hip -- one-image FSR at supports 8, 16 and 24: one workgroup
-// of one wavefront per block (fsr_block_sg.h), or at S = 8 with B <= 4 eight
-// blocks per wavefront (fsr_block_multi.h); both give bitwise the same
-// result.
+// of one wavefront per block (fsr_block_sg.h; at S = 24 fsr_block_s24.h), or
+// at S = 8 with B <= 4 eight blocks per wavefront (fsr_block_multi.h; bitwise
+// the result of the one-block routine).
 #include "fsr_block.h"
 #include "fsr_block_multi.h"
+#include "fsr_block_s24.h"
 #include "fsr_block_sg.h"
 
 namespace fsr {
@@ -15,6 +16,15 @@ __global__ __launch_bounds__(64) void fsr_plain_sg(PlainLaunch p) {
     const int64_t blk = xcd_contiguous(blockIdx.x, p.n_blocks);
     reconstruct_block_sg<S, false, kArgmax>(plain_job(p, blk), p.block, p.border, p.gamma, p.tab, lds,
                                             reinterpret_cast<uint2*>(lds + SgShape<S>::kLdsFloats));
+}
+
+template <int kArgmax = kArgmaxWave>
+__global__ __launch_bounds__(64) void fsr_plain_s24(PlainLaunch p) {
+    constexpr int kExtra = kArgmax == kArgmaxLds ? 2 * S24::kArgmaxPairs : 0;
+    __shared__ __align__(16) float lds[S24::kLdsFloats + kExtra];
+    const int64_t blk = xcd_contiguous(blockIdx.x, p.n_blocks);
+    reconstruct_block_s24<false, kArgmax>(plain_job(p, blk), p.block, p.border, p.gamma, p.tab, lds,
+                                          reinterpret_cast<uint2*>(lds + S24::kLdsFloats));
 }
 
 template <int S, int T>
@@ -54,7 +64,7 @@ hipError_t launch_plain_sg(const PlainLaunch& p, hipStream_t stream) {
         switch (p.support) {
         case 8: hipLaunchKernelGGL((fsr_plain_sg<8, kArgmaxLds>), grid, block, 0, stream, p); break;
         case 16: hipLaunchKernelGGL((fsr_plain_sg<16, kArgmaxLds>), grid, block, 0, stream, p); break;
-        case 24: hipLaunchKernelGGL((fsr_plain_sg<24, kArgmaxLds>), grid, block, 0, stream, p); break;
+        case 24: hipLaunchKernelGGL((fsr_plain_s24<kArgmaxLds>), grid, block, 0, stream, p); break;
         default: return hipErrorInvalidValue;
         }
         return hipGetLastError();
@@ -66,7 +76,7 @@ hipError_t launch_plain_sg(const PlainLaunch& p, hipStream_t stream) {
     switch (p.support) {
     case 8: hipLaunchKernelGGL(fsr_plain_sg<8>, grid, block, 0, stream, p); break;
     case 16: hipLaunchKernelGGL(fsr_plain_sg<16>, grid, block, 0, stream, p); break;
-    case 24: hipLaunchKernelGGL(fsr_plain_sg<24>, grid, block, 0, stream, p); break;
+    case 24: hipLaunchKernelGGL(fsr_plain_s24<>, grid, block, 0, stream, p); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
