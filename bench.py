@@ -92,9 +92,9 @@ def parse():
                     help="skip the split-bf16 vs FP32-FFT comparison on the 3840x2160 frame")
     ap.add_argument("--serve-max-batch", type=int, default=2,
                     help="frames per launch of the continuous-batching server")
-    ap.add_argument("--serve-requests", type=int, default=2400,
-                    help="requests of the served comparison (0 skips it); the stated workload "
-                         "is 10,000 (about 42 s per mode)")
+    ap.add_argument("--serve-requests", type=int, default=10000,
+                    help="requests of the served comparison, the serving workload's 10,000 by "
+                         "default (about 42 s per mode; 0 skips it)")
     ap.add_argument("--tuning-cache", default=None, metavar="PATH",
                     help="load the batched path's autotune results from PATH if it exists, and "
                          "write them back after the run")
@@ -105,6 +105,12 @@ def parse():
     ap.add_argument("--sweep", action="store_true",
                     help="only run the paper's 640-point parameter grid (S, I, rho, gamma) on a "
                          "1200x1200 frame and print it as one JSON object")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="time the headline launches and nothing else (for profiler runs of "
+                         "that one configuration)")
+    ap.add_argument("--support", type=int, default=32, choices=(8, 16, 24, 32),
+                    help="support S of the timed launches (B = 4, L = (S - 4) / 2); the "
+                         "headline configuration is S = 32, others serve per-support profiles")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (a kernel of known "
                          "traffic, used to scale the FETCH_SIZE / WRITE_SIZE counters)")
@@ -261,6 +267,14 @@ def bench_argmax_ablation(ctx, img32, mask, params, steps: int = 5):
     by_support[f"S{params.block + 2 * params.border}"] = {
         "register_ms": res["register_argmax"]["ms"], "lds_ms": res["lds_argmax"]["ms"],
         "speedup_register_over_lds": res["speedup_register_over_lds"]}
+    # the register path of each support against the FP32 vector peak, with the
+    # same algorithmic flop count as the headline line (B = 4)
+    blocks = -(-img32.shape[0] // 4) * -(-img32.shape[1] // 4)
+    for key, t in by_support.items():
+        flops = algorithmic_flops_per_block(int(key[1:]), 4, params.iterations) * blocks
+        tf = flops / (t["register_ms"] * 1e-3) / 1e12
+        t["register_tflop_s"] = round(tf, 3)
+        t["register_frac_of_peak"] = round(tf / PEAK_FP32_TFLOPS, 4)
     res["by_support"] = by_support
     return res
 
@@ -692,7 +706,8 @@ def main():
     tm = torch.from_numpy(mask).to(dev)
     out = torch.empty_like(ti)
     ctx = fsr.Context(0)
-    params = fsr.make_params(block=w.block, border=w.border, iterations=w.iterations, rho=w.rho,
+    border = w.border if args.support == w.support else (args.support - w.block) // 2
+    params = fsr.make_params(block=w.block, border=border, iterations=w.iterations, rho=w.rho,
                              gamma=w.gamma)
     stream = torch.cuda.current_stream(dev)
 
@@ -716,7 +731,7 @@ def main():
     pixels = w.height * w.width
     value = pixels / (ms_per_step * 1e-3) / 1e6
 
-    flops = algorithmic_flops_per_block(w.support, w.block, w.iterations) * w.n_blocks
+    flops = algorithmic_flops_per_block(args.support, w.block, w.iterations) * w.n_blocks
     achieved = flops / (ms_per_step * 1e-3) / 1e12
 
     # quality of this run (vs. the ground-truth frame)
@@ -753,6 +768,15 @@ def main():
                      "avg_launch_ms": round(ms_per_step, 5),
                      "traffic": measured_traffic()},
     }
+    if args.support != w.support:
+        res["config"]["workload"] += f"; timed at S={args.support} (B=4, L={border}) instead"
+        res["roofline"]["kernel"] = "fsr_plain_multi" if args.support == 8 else (
+            "fsr_plain_s24" if args.support == 24 else "fsr_plain_sg")
+        res["roofline"]["traffic"] = None
+    if args.only_headline:
+        ctx.close()
+        print(json.dumps(res), flush=True)
+        return
     res["argmax_ablation"] = bench_argmax_ablation(ctx, img32, mask, params)
     res["multiresolution"] = bench_multiresolution(ctx)
     if not args.no_reuse:

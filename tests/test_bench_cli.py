@@ -29,9 +29,11 @@ def test_every_flag_parses(monkeypatch):
         "bench.py", "--gpus", "1", "--steps", "3", "--warmup", "1", "--no-cpu-baseline",
         "--cpu-blocks", "100", "--no-batched", "--no-precision", "--no-reuse", "--reuse-frames", "4,8",
         "--serve-max-batch", "2", "--serve-requests", "10", "--tuning-cache", "/tmp/t.json",
-        "--serve-log", "/tmp/s.jsonl", "--realtime-seconds", "0", "--copy-calibration", "0"])
+        "--serve-log", "/tmp/s.jsonl", "--realtime-seconds", "0", "--copy-calibration", "0",
+        "--only-headline", "--support", "24"])
     a = bench.parse()
     assert a.steps == 3 and a.reuse_frames == "4,8" and a.serve_log == "/tmp/s.jsonl"
+    assert a.only_headline and a.support == 24
 
 
 def test_every_name_a_function_reads_is_defined():
