@@ -667,6 +667,7 @@ def bench_served(ctx, n_requests: int, rate_hz: float = 240.0, budget: int = 4 <
                                          "arrival_s": round(req.arrival_s, 6), "submit_s": row[0],
                                          "admit_s": row[1], "launch_s": row[2], "done_s": row[3],
                                          "latency_ms": round(float(lat[k]), 4)}) + "\n")
+        print(f"[bench] served, {name}: {len(trace)} requests done", file=sys.stderr, flush=True)
         out[name] = {"p50_ms": round(float(np.percentile(lat, 50)), 3),
                      "p99_ms": round(float(np.percentile(lat, 99)), 3),
                      "max_ms": round(float(lat.max()), 3),
@@ -777,30 +778,48 @@ def main():
         ctx.close()
         print(json.dumps(res), flush=True)
         return
+    t_leg = time.perf_counter()
+
+    def leg_done(name):
+        # one progress line per finished leg (stderr: stdout carries the JSON line only)
+        nonlocal t_leg
+        now = time.perf_counter()
+        print(f"[bench] {name} done in {now - t_leg:.1f} s", file=sys.stderr, flush=True)
+        t_leg = now
+
+    leg_done("headline")
     res["argmax_ablation"] = bench_argmax_ablation(ctx, img32, mask, params)
+    leg_done("argmax ablation")
     res["multiresolution"] = bench_multiresolution(ctx)
+    leg_done("multiresolution")
     if not args.no_reuse:
         counts = tuple(int(x) for x in args.reuse_frames.split(",") if x.strip())
         if any(n < 4 or n % 4 for n in counts):
             sys.exit("--reuse-frames takes multiples of 4")
         res["reuse_variant"] = bench_reuse(ctx, img32, mask, params, frame_counts=counts)
+        leg_done("reuse variant")
     if args.tuning_cache and os.path.exists(args.tuning_cache):
         with open(args.tuning_cache) as fh:
             fsr.fsr_batch_tuning_import(ctx, fh.read())
     if not args.no_batched:
         res["batched"] = bench_batched(ctx)
+        leg_done("batched")
     if args.tuning_cache:
         with open(args.tuning_cache, "w") as fh:
             fh.write(fsr.fsr_batch_tuning_export(ctx) + "\n")
     if not args.no_precision:
         res["precision"] = bench_precision(ctx)
+        leg_done("precision")
     if args.serve_requests > 0:
         res["served"] = bench_served(ctx, args.serve_requests, max_batch=args.serve_max_batch,
                                      log_path=args.serve_log)
+        leg_done("served")
     if args.realtime_seconds > 0:
         res["realtime_s16"] = bench_realtime_s16(ctx, args.realtime_seconds)
+        leg_done("real-time S = 16")
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(img32, mask, w, args.cpu_blocks)
+        leg_done("cpu baseline")
     ctx.close()
     print(json.dumps(res), flush=True)
 
