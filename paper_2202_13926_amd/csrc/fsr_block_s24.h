@@ -24,16 +24,16 @@
 //
 // LDS per wavefront: the DFT table (S^2 float2) and a scratch area (S^2
 // float2: the tile, then the first pass, then the spectrum) during the
-// transforms; during the iterations W with its first 16 rows and columns
-// repeated, 40 x 40 entries (entry (R, C) = W[R mod S][C mod S]), 12.5 KiB.
-// A lane's nine entries (r0 + 8 i, c0 + 8 j) of the shifted spectrum of
-// Eqs. 14-15 then lie at immediate offsets from one base, with r0 and c0
-// the lane's row and column shifted and wrapped once per iteration.  Rows
-// and columns duplicated in full (48 x 48 at a pitch of 52, 19.5 KiB) make
-// that base a uniform offset, but leave two wavefronts per SIMD instead of
-// three: measured on the 1080p frame at I = 100, 3.50 ms in full, 2.97 ms
-// with only the rows in full, 2.57 ms as here (the 48-lane layout of
-// fsr_block_sg.h: 3.27 ms).
+// transforms; during the iterations W with its columns repeated once (24 x
+// 48 entries, entry (R, C) = W[R][C mod S]), in the same 9 KiB.  Slot (i, j)
+// of lane (a, b) reads row (a - u + 8 i) mod S, wrapped per row slot i, and
+// column b + 8 j + S - v, which needs no wrap: three row bases per
+// iteration, each with immediate offsets for j.  The layouts measured on
+// the 1080p frame at I = 100: this one 2.40 ms (four and more wavefronts
+// per SIMD); rows and columns both repeated up to 40 (12.5 KiB, three per
+// SIMD, two wraps) 2.57 ms; both repeated in full (48 x 48 at a pitch of 52,
+// 19.5 KiB, two per SIMD, a uniform shift) 3.50 ms; the 48-lane layout of
+// fsr_block_sg.h 3.27 ms.
 #pragma once
 
 #include "fsr_block.h"
@@ -44,11 +44,10 @@ namespace fsr {
 struct S24 {
     static constexpr int S = 24;
     static constexpr int NS = 9;                  // slots per lane
-    static constexpr int kDup = 40;               // table rows and columns: 24 + 16 copies
-    static constexpr int kPitch = 40;             // W table pitch, float2
+    static constexpr int kPitch = 2 * S;          // W table: S rows of 2S entries (float2)
     static constexpr int kTabFloats = 2 * S * S;  // DFT table, then scratch
-    static constexpr int kLdsFloats = 2 * kDup * kPitch;
-    static_assert(2 * kTabFloats <= kLdsFloats, "transforms fit under the W table");
+    static constexpr int kLdsFloats = 2 * S * kPitch;
+    static_assert(2 * kTabFloats <= kLdsFloats, "transforms fit in the W table's space");
     static constexpr int kArgmaxPairs = 1024;     // 576 (key, lane) pairs, padded to 2^10
 };
 
@@ -245,11 +244,7 @@ __device__ __forceinline__ void reconstruct_block_s24(const BlockJob& jb, int B,
             const int k = a + 8 * (s / 3), l = b + 8 * (s % 3);
             const float2 wv = make_float2(wr[s], wi[s]);
             wtab[k * P + l] = wv;
-            if (l + S < S24::kDup) wtab[k * P + l + S] = wv;
-            if (k + S < S24::kDup) {
-                wtab[(k + S) * P + l] = wv;
-                if (l + S < S24::kDup) wtab[(k + S) * P + l + S] = wv;
-            }
+            wtab[k * P + l + S] = wv;
         }
         // lane constants kept as computed here
         const int a8p = opaque(8 * P * a), b8 = opaque(8 * b);
@@ -317,18 +312,24 @@ __device__ __forceinline__ void reconstruct_block_s24(const BlockJob& jb, int B,
             acc = fmaf(ci, ei, acc);
 
             // residual (Eqs. 12, 14-15): bin (k, l) = (a + 8 i, b + 8 j) reads
-            // W[(k - u) mod S][(l - v) mod S], table entry (r0 + 8 i, c0 + 8 j)
-            // with r0 = (a - u) mod S and c0 = (b - v) mod S (below 40), so the
-            // slot's entry is an immediate offset from the lane's base.  The
-            // wrap of 8 P (a - u) into [0, 8 P S) is a minimum of unsigned
-            // values: the difference itself when a >= u, else it plus 8 P S
-            const int r = a8p - 8 * P * u, cc = b8 - 8 * v;
-            const int addr = (int)umin((uint32_t)r, (uint32_t)(r + 8 * P * S)) +
-                             (int)umin((uint32_t)cc, (uint32_t)(cc + 8 * S));
-            const float2* wrow = reinterpret_cast<const float2*>(wbytes + addr);
+            // W[(k - u) mod S][(l - v) mod S], table entry
+            // ((a - u + 8 i) mod S, b + 8 j + S - v).  A row offset
+            // 8 P x is wrapped into [0, 8 P S) by a minimum of unsigned
+            // values (x itself when in range, else x -/+ S rows)
+            const int r = a8p - 8 * P * u;
+            const uint32_t r0 = umin((uint32_t)r, (uint32_t)(r + 8 * P * S));
+            const uint32_t r1a = r0 + 64 * P, r2a = r0 + 128 * P;
+            const int cbase = b8 + 8 * (S - v);
+            const int ad0 = (int)r0 + cbase;
+            const int ad1 = (int)umin(r1a, r1a - 8 * P * S) + cbase;
+            const int ad2 = (int)umin(r2a, r2a - 8 * P * S) + cbase;
+            const float2* wrow0 = reinterpret_cast<const float2*>(wbytes + ad0);
+            const float2* wrow1 = reinterpret_cast<const float2*>(wbytes + ad1);
+            const float2* wrow2 = reinterpret_cast<const float2*>(wbytes + ad2);
+            const float2* wrows[3] = {wrow0, wrow1, wrow2};
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
-                const float2 w = wrow[8 * P * (s / 3) + 8 * (s % 3)];
+                const float2 w = wrows[s / 3][8 * (s % 3)];
                 xr[s] = fmaf(-cr, w.x, xr[s]);
                 xr[s] = fmaf(ci, w.y, xr[s]);
                 xi[s] = fmaf(-cr, w.y, xi[s]);
