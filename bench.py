@@ -248,11 +248,13 @@ def bench_argmax_ablation(ctx, img32, mask, params, steps: int = 5):
     # the same comparison over the supports of Fig. 3 (B = 4, L = 2, 6, 10);
     # at S = 8 the register path takes eight blocks per wavefront
     by_support = {}
-    for L in (2, 6, 10):
-        times = {}
-        for tag, flags in (("register_ms", 0), ("lds_ms", fsr.FSR_FLAG_LDS_ARGMAX)):
-            p = fsr.make_params(block=4, border=L, iterations=params.iterations, rho=params.rho,
-                                gamma=params.gamma, flags=flags)
+    support_variants = {(L, tag): fsr.make_params(block=4, border=L, iterations=params.iterations,
+                                                  rho=params.rho, gamma=params.gamma, flags=flags)
+                        for L in (2, 6, 10)
+                        for tag, flags in (("register_ms", 0), ("lds_ms", fsr.FSR_FLAG_LDS_ARGMAX))}
+    best_s = {}
+    for _ in range(2):                     # as above: alternate, keep each one's best
+        for key, p in support_variants.items():
             fsr.fsr_reconstruct(ctx, ti, tm, o, p, None, stream)
             torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -261,7 +263,9 @@ def bench_argmax_ablation(ctx, img32, mask, params, steps: int = 5):
                 fsr.fsr_reconstruct(ctx, ti, tm, o, p, None, stream)
             e1.record(stream)
             torch.cuda.synchronize()
-            times[tag] = round(e0.elapsed_time(e1) / steps, 4)
+            best_s[key] = min(best_s.get(key, 1e30), e0.elapsed_time(e1) / steps)
+    for L in (2, 6, 10):
+        times = {tag: round(best_s[(L, tag)], 4) for tag in ("register_ms", "lds_ms")}
         times["speedup_register_over_lds"] = round(times["lds_ms"] / times["register_ms"], 3)
         by_support[f"S{4 + 2 * L}"] = times
     by_support[f"S{params.block + 2 * params.border}"] = {
