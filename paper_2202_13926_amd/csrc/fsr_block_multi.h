@@ -30,7 +30,12 @@
 //
 // LDS per wavefront: the DFT table (S^2 float2) and per block the tile, then
 // the first DFT pass (S^2 float2); during the iterations per block W with
-// duplicated rows (2S x S float2), over the same space.
+// duplicated rows (2S x S float2), over the same space, the blocks' rows
+// interleaved.  One read takes a row of S entries for each block, at the
+// block's own u; with the tables one after another a row of 16 words starts
+// at a bank that depends on u alone, so blocks whose u agree mod 4 collide,
+// while interleaved the block decides the bank (0.317 against 0.335 ms for
+// the 1080p frame at I = 100, the same output).
 #pragma once
 
 #include "fsr_block.h"
@@ -296,16 +301,18 @@ __device__ __forceinline__ void reconstruct_multi(const MultiJob& im, int B, int
     const float2 tw = ftab[S + c];
     const int tw_re = __float_as_int(tw.x), tw_im = __float_as_int(tw.y);
     wave_sync();
-    // W with duplicated rows: entry (R, C) of block b holds W[R mod S][C]
-    float2* wtab = reinterpret_cast<float2*>(lds) + b * 2 * S * S;
+    // W with duplicated rows: entry (R, C) of block b holds W[R mod S][C],
+    // at (R NB + b) S + C: the rows of the blocks interleaved, so that one
+    // read (a row per block, each at its own u) spreads over the banks by b
+    float2* wtab = reinterpret_cast<float2*>(lds) + b * S;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const float2 wv = make_float2(wr[s], wi[s]);
-        wtab[s * S + c] = wv;
-        wtab[(s + S) * S + c] = wv;
+        wtab[s * NB * S + c] = wv;
+        wtab[(s + S) * NB * S + c] = wv;
     }
     const char* wbytes = reinterpret_cast<const char*>(lds);
-    const int wb = opaque(8 * b * 2 * S * S);   // byte offset of this block's table
+    const int wb = opaque(8 * b * S);   // byte offset of this block's rows
     const int first4 = opaque(4 * first);
     wave_sync();
 
@@ -343,10 +350,10 @@ __device__ __forceinline__ void reconstruct_multi(const MultiJob& im, int B, int
         // residual (Eqs. 12, 14-15): bin (s, c) reads entry (s - u + S,
         // (c - v) mod S) of its block's table
         const float2* wrow = reinterpret_cast<const float2*>(
-            wbytes + wb + 8 * ((S - u) * S + ((c - v) & (S - 1))));
+            wbytes + wb + 8 * ((S - u) * NB * S + ((c - v) & (S - 1))));
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            const float2 w = wrow[S * s];
+            const float2 w = wrow[NB * S * s];
             xr[s] = fmaf(-cr, w.x, xr[s]);
             xr[s] = fmaf(ci, w.y, xr[s]);
             xi[s] = fmaf(-cr, w.y, xi[s]);

@@ -24,15 +24,23 @@
 //
 // LDS per wavefront: the DFT table (S^2 float2) and a scratch area (S^2
 // float2: the tile, then the first pass, then the spectrum) during the
-// transforms; during the iterations W with its columns repeated once (24 x
-// 48 entries, entry (R, C) = W[R][C mod S]), in the same 9 KiB.  Slot (i, j)
-// of lane (a, b) reads row (a - u + 8 i) mod S, wrapped per row slot i, and
-// column b + 8 j + S - v, which needs no wrap: three row bases per
-// iteration, each with immediate offsets for j.  The layouts measured on
-// the 1080p frame at I = 100: this one 2.40 ms (four and more wavefronts
-// per SIMD); rows and columns both repeated up to 40 (12.5 KiB, three per
-// SIMD, two wraps) 2.57 ms; both repeated in full (48 x 48 at a pitch of 52,
-// 19.5 KiB, two per SIMD, a uniform shift) 3.50 ms; the 48-lane layout of
+// transforms; during the iterations W with its columns repeated once (24
+// rows of 48 entries, entry (R, C) = W[R][C mod S]) at a row pitch of 52
+// entries, 9.75 KiB.  Slot (i, j) of lane (a, b) reads row (a - u + 8 i)
+// mod S, wrapped per row slot i, and column b + 8 j + S - v, which needs no
+// wrap: three row bases per iteration, each with immediate offsets for j.
+// One read covers eight consecutive rows (mod S) of eight consecutive
+// entries; at a pitch of 52 entries (104 words, 40 mod 64) the eight rows
+// start 0, 40, 16, 56, 32, 8, 48, 24 words into the 64 banks, so every bank
+// serves two words, the fewest for 64 lanes of 8 bytes, and every half
+// wavefront (four rows) covers the 32 banks of a half twice.  A pitch of 48
+// (96 words) starts the rows alternately at 0 and 32: 3,072 bank-conflict
+// cycles per block.  Measured on the 1080p frame at I = 100, pitches timed
+// side by side: pitch 52 2.40 ms, 48 2.45-2.47 ms, 50 2.48 ms on one box;
+// 56 (10.5 KiB, fewer resident wavefronts) 2.51 ms against 2.41 ms at 48 on
+// another.  Earlier layouts against 2.40 ms at pitch 48: rows and columns
+// both repeated up to 40 (12.5 KiB, two wraps) 2.57 ms; both repeated in
+// full (48 x 48, 19.5 KiB, a uniform shift) 3.50 ms; the 48-lane layout of
 // fsr_block_sg.h 3.27 ms.
 #pragma once
 
@@ -44,7 +52,7 @@ namespace fsr {
 struct S24 {
     static constexpr int S = 24;
     static constexpr int NS = 9;                  // slots per lane
-    static constexpr int kPitch = 2 * S;          // W table: S rows of 2S entries (float2)
+    static constexpr int kPitch = 52;             // W table: S rows of 2S entries (float2), this pitch
     static constexpr int kTabFloats = 2 * S * S;  // DFT table, then scratch
     static constexpr int kLdsFloats = 2 * S * kPitch;
     static_assert(2 * kTabFloats <= kLdsFloats, "transforms fit in the W table's space");
