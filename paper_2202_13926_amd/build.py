@@ -18,7 +18,7 @@ LIB = os.path.join(PKG, "libfsr.so")
 
 SOURCES = ["fsr_api.cpp", "fsr_batched.cpp", "fsr_serve.cpp", "fsr_plain.hip", "fsr_plain_sg.hip",
            "fsr_batched.hip", "fsr_reuse.hip"]
-HEADERS = ["fsr_device.h", "fsr_block.h", "fsr_block_sg.h", "fsr_block_s24.h", "fsr_block_multi.h", "fsr_mfma.h", "fsr_internal.h",
+HEADERS = ["fsr_device.h", "fsr_block.h", "fsr_block_sg.h", "fsr_block_s24.h", "fsr_block_multi.h", "fsr_block_split4.h", "fsr_mfma.h", "fsr_internal.h",
            "fsr_batch_internal.h", "fsr_runtime.h", "fsr_sched.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -15,6 +15,7 @@
 #include <algorithm>
 
 #include "fsr_block.h"
+#include "fsr_block_split4.h"
 
 namespace fsr {
 
@@ -38,6 +39,32 @@ __global__ __launch_bounds__(64) void fsr_reuse_s32(PlainLaunch p, float delta, 
     reconstruct_block<kDftFft32, kArgmaxWave, false, true>(jb, p.block, p.border, p.gamma, p.tab, lds);
 }
 
+// The same blocks with four wavefronts each (fsr_block_split4.h), for steps
+// too small to fill the device; bitwise the same result.
+__global__ __launch_bounds__(256) void fsr_reuse_split4_s32(PlainLaunch p, float delta, int32_t step,
+                                                            int32_t by_lo, int32_t slope, int64_t frame_stride,
+                                                            int64_t log_stride) {
+    __shared__ __align__(16) float lds[kLdsFloats];
+    __shared__ Split4Lds sh;
+    const int by = by_lo + (int)blockIdx.x;
+    const int bx = step - slope * by;
+    const int64_t f = blockIdx.y;
+    BlockJob jb = plain_job(p, (int64_t)by * p.img.nbx + bx);
+    jb.image += f * frame_stride;
+    jb.mask += f * frame_stride;
+    jb.out += f * frame_stride;
+    if (jb.log != nullptr) jb.log += f * log_stride;
+    jb.delta = delta;
+    reconstruct_block_reuse_split4(jb, p.block, p.border, p.gamma, p.tab, lds, sh);
+}
+
+// Steps with at most this many blocks (over all frames) run four wavefronts
+// per block.  Measured on 1080p frames (at most 96 blocks per step and
+// frame), ms per call of 1 / 2 / 3 / 4 / 8 frames: one wavefront per block
+// 105.4 / 105.8 / 107.5 / 108.1 / 108.8; four for every step 97.1 / 97.2 /
+// 101.1 / 102.2 / 111.4.
+constexpr int64_t kSplit4MaxBlocks = 512;
+
 int64_t reuse_steps(int32_t height, int32_t width, int32_t block, int32_t border) {
     const int64_t nby = (height + block - 1) / block, nbx = (width + block - 1) / block;
     const int64_t slope = (border + block - 1) / block + 1;
@@ -57,9 +84,13 @@ hipError_t launch_reuse(const PlainLaunch& p, float delta, int32_t n_frames, int
         const int64_t lo = over > 0 ? (over + slope - 1) / slope : 0;
         const int64_t hi = std::min<int64_t>(nby - 1, t / slope);
         if (hi < lo) continue;   // no block at this step (possible when slope > nbx)
-        hipLaunchKernelGGL(fsr_reuse_s32, dim3((unsigned)(hi - lo + 1), (unsigned)n_frames), dim3(64), 0,
-                           stream, p, delta, (int32_t)t, (int32_t)lo, (int32_t)slope, frame_stride,
-                           log_stride);
+        const dim3 grid((unsigned)(hi - lo + 1), (unsigned)n_frames);
+        if ((hi - lo + 1) * (int64_t)n_frames <= kSplit4MaxBlocks)
+            hipLaunchKernelGGL(fsr_reuse_split4_s32, grid, dim3(256), 0, stream, p, delta, (int32_t)t,
+                               (int32_t)lo, (int32_t)slope, frame_stride, log_stride);
+        else
+            hipLaunchKernelGGL(fsr_reuse_s32, grid, dim3(64), 0, stream, p, delta, (int32_t)t, (int32_t)lo,
+                               (int32_t)slope, frame_stride, log_stride);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -320,18 +320,23 @@ def test_frames_equal_one_frame_calls(ctx, stride_pad, frame_pad):
 
 
 def test_frames_at_full_size(ctx):
-    announce("reuse over 3 frames of 1920x1080 vs one-frame calls")
+    # six frames of 96 blocks per step: the steps with more than 512 blocks
+    # over all frames run one wavefront per block, the one-frame calls run
+    # four per block on every step; both must give the same bits
+    announce("reuse over 6 frames of 1920x1080 vs one-frame calls")
     w = synth.workload("fhd_quarter")
     img, mask = w.inputs()
     img32 = img.astype(np.float32)
-    imgs = np.stack([img32, img32[::-1].copy(), img32[:, ::-1].copy()])
-    masks = np.stack([mask, mask[:, ::-1].copy(), mask[::-1].copy()])
+    imgs = np.stack([img32, img32[::-1].copy(), img32[:, ::-1].copy(), img32[::-1, ::-1].copy(),
+                     np.roll(img32, 7, axis=1), np.roll(img32, 5, axis=0)])
+    masks = np.stack([mask, mask[:, ::-1].copy(), mask[::-1].copy(), np.roll(mask, 3, axis=0),
+                      mask[::-1, ::-1].copy(), np.roll(mask, 9, axis=1)])
     p = fsr.make_params()
     ti, tm = torch.from_numpy(imgs).to(DEV), torch.from_numpy(masks).to(DEV)
     out = torch.empty_like(ti)
     fsr.fsr_reconstruct_reuse_frames(ctx, ti, tm, out, p, 0.5)
     torch.cuda.synchronize()
     got = out.cpu().numpy()
-    for f in range(3):
+    for f in range(len(imgs)):
         ref, _ = run(ctx, imgs[f], masks[f], p, 0.5)
         assert np.array_equal(got[f], ref), f"frame {f}"
