@@ -14,9 +14,9 @@
 // workgroup barrier (double-buffered, so one barrier per iteration
 // suffices), and every wavefront takes the largest: the same bin as the
 // one-wavefront routine, whose keys are unique across slots.  Each bin's
-// residual update is the same arithmetic in the same order, and wavefront
-// 0 accumulates the target model as before, so the result is bitwise that
-// of the one-wavefront routine.
+// residual update is the same arithmetic in the same order, and every
+// wavefront accumulates the target model as before (wavefront 0 writes
+// it), so the result is bitwise that of the one-wavefront routine.
 #pragma once
 
 #include "fsr_block.h"
@@ -174,28 +174,31 @@ __device__ __forceinline__ void reconstruct_block_reuse_split4(const BlockJob& j
             const int idx = 64 * (15 - (int)(mxw & 15u)) + lnw;
             const int u = idx >> 5, v = idx & 31;
             const float cr = gi * pr, ci = gi * pim;    // gamma * p (Eqs. 10-11)
-            if (q == 0) {
-                if (jb.log != nullptr && lane == 0) jb.log[it] = (uint16_t)idx;
-                // model: g += gamma p exp(+j 2 pi (u m + v n) / S) on the target
-                const int q4 = dot2_u16(u | (v << 16), tmn4);
-                const float er = __int_as_float(__builtin_amdgcn_ds_bpermute(q4, tw_re));
-                const float ei = __int_as_float(__builtin_amdgcn_ds_bpermute(q4, tw_im));
-                acc = fmaf(cr, er, acc);
-                acc = fmaf(ci, ei, acc);
-            }
             // residual (Eqs. 12, 14-15) on this wavefront's slots, as in
             // fsr_block.h: slot 4q + s reads duplicated row h + 32 - u +
-            // 2 (4q + s), column (c - v) mod 32
+            // 2 (4q + s), column (c - v) mod 32.  The reads go out first so
+            // that the model's lane exchange waits alongside them.
             const int woff = sub_low_byte(hc8 + (8192 - 256 * u), 8 * v);
             const float2* wrow = reinterpret_cast<const float2*>(reinterpret_cast<const char*>(wtab) + woff);
+            float2 w[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) w[s] = wrow[64 * s];
+            // model: g += gamma p exp(+j 2 pi (u m + v n) / S) on the target;
+            // every wavefront computes it (no branch in the loop's chain),
+            // wavefront 0's is the one written
+            const int q4 = dot2_u16(u | (v << 16), tmn4);
+            const float er = __int_as_float(__builtin_amdgcn_ds_bpermute(q4, tw_re));
+            const float ei = __int_as_float(__builtin_amdgcn_ds_bpermute(q4, tw_im));
+            acc = fmaf(cr, er, acc);
+            acc = fmaf(ci, ei, acc);
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
-                const float2 w = wrow[64 * s];
-                vr[s] = fmaf(-cr, w.x, vr[s]);
-                vr[s] = fmaf(ci, w.y, vr[s]);
-                vi[s] = fmaf(-cr, w.y, vi[s]);
-                vi[s] = fmaf(-ci, w.x, vi[s]);
+                vr[s] = fmaf(-cr, w[s].x, vr[s]);
+                vr[s] = fmaf(ci, w[s].y, vr[s]);
+                vi[s] = fmaf(-cr, w[s].y, vi[s]);
+                vi[s] = fmaf(-ci, w[s].x, vi[s]);
             }
+            if (q == 0 && jb.log != nullptr && lane == 0) jb.log[it] = (uint16_t)idx;
         }
     } else if (q == 0 && jb.log != nullptr) {
         for (int it = lane; it < iters; it += 64) jb.log[it] = (uint16_t)0xFFFF;

@@ -61,8 +61,8 @@ __global__ __launch_bounds__(256) void fsr_reuse_split4_s32(PlainLaunch p, float
 // Steps with at most this many blocks (over all frames) run four wavefronts
 // per block.  Measured on 1080p frames (at most 96 blocks per step and
 // frame), ms per call of 1 / 2 / 3 / 4 / 8 frames: one wavefront per block
-// 105.4 / 105.8 / 107.5 / 108.1 / 108.8; four for every step 97.1 / 97.2 /
-// 101.1 / 102.2 / 111.4.
+// 105.4 / 105.8 / 107.5 / 108.1 / 108.8; four for every step 92.0 / 92.0 /
+// 97.8 / 99.1 / 110.7.
 constexpr int64_t kSplit4MaxBlocks = 512;
 
 int64_t reuse_steps(int32_t height, int32_t width, int32_t block, int32_t border) {
