@@ -35,8 +35,10 @@
 // serves two words, the fewest for 64 lanes of 8 bytes, and every half
 // wavefront (four rows) covers the 32 banks of a half twice.  A pitch of 48
 // (96 words) starts the rows alternately at 0 and 32: 3,072 bank-conflict
-// cycles per block.  Measured on the 1080p frame at I = 100, pitches timed
-// side by side: pitch 52 2.40 ms, 48 2.45-2.47 ms, 50 2.48 ms on one box;
+// cycles per block.  Measured on the 1080p frame at I = 100 (before the W
+// reads were issued ahead of the model's lane exchange, which took 2.40 to
+// 2.33-2.37 ms), pitches timed side by side: pitch 52 2.40 ms, 48
+// 2.45-2.47 ms, 50 2.48 ms on one box;
 // 56 (10.5 KiB, fewer resident wavefronts) 2.51 ms against 2.41 ms at 48 on
 // another.  Earlier layouts against 2.40 ms at pitch 48: rows and columns
 // both repeated up to 40 (12.5 KiB, two wraps) 2.57 ms; both repeated in
@@ -312,13 +314,6 @@ __device__ __forceinline__ void reconstruct_block_s24(const BlockJob& jb, int B,
             const float cr = gi * pr, ci = gi * pim;    // gamma * p (Eqs. 10-11)
             if (jb.log != nullptr && lane == 0) jb.log[it] = (uint16_t)(u * S + v);
 
-            // model: g += gamma p exp(+j 2 pi (u m + v n) / S) on the target
-            const int q4 = 4 * mod_small<S>(dot2_u16(u | (v << 16), tmn));
-            const float er = __int_as_float(__builtin_amdgcn_ds_bpermute(q4, tw_re));
-            const float ei = __int_as_float(__builtin_amdgcn_ds_bpermute(q4, tw_im));
-            acc = fmaf(cr, er, acc);
-            acc = fmaf(ci, ei, acc);
-
             // residual (Eqs. 12, 14-15): bin (k, l) = (a + 8 i, b + 8 j) reads
             // W[(k - u) mod S][(l - v) mod S], table entry
             // ((a - u + 8 i) mod S, b + 8 j + S - v).  A row offset
@@ -335,13 +330,24 @@ __device__ __forceinline__ void reconstruct_block_s24(const BlockJob& jb, int B,
             const float2* wrow1 = reinterpret_cast<const float2*>(wbytes + ad1);
             const float2* wrow2 = reinterpret_cast<const float2*>(wbytes + ad2);
             const float2* wrows[3] = {wrow0, wrow1, wrow2};
+            // the reads go out before the model's lane exchange, so that the
+            // two wait together
+            float2 w[NS];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) w[s] = wrows[s / 3][8 * (s % 3)];
+            // model: g += gamma p exp(+j 2 pi (u m + v n) / S) on the target
+            const int q4 = 4 * mod_small<S>(dot2_u16(u | (v << 16), tmn));
+            const float er = __int_as_float(__builtin_amdgcn_ds_bpermute(q4, tw_re));
+            const float ei = __int_as_float(__builtin_amdgcn_ds_bpermute(q4, tw_im));
+            acc = fmaf(cr, er, acc);
+            acc = fmaf(ci, ei, acc);
+
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
-                const float2 w = wrows[s / 3][8 * (s % 3)];
-                xr[s] = fmaf(-cr, w.x, xr[s]);
-                xr[s] = fmaf(ci, w.y, xr[s]);
-                xi[s] = fmaf(-cr, w.y, xi[s]);
-                xi[s] = fmaf(-ci, w.x, xi[s]);
+                xr[s] = fmaf(-cr, w[s].x, xr[s]);
+                xr[s] = fmaf(ci, w[s].y, xr[s]);
+                xi[s] = fmaf(-cr, w[s].y, xi[s]);
+                xi[s] = fmaf(-ci, w[s].x, xi[s]);
             }
         }
         wave_sync();   // the LDS is reused by the next block of a persistent wave
