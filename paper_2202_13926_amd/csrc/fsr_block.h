@@ -375,6 +375,21 @@ __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int
             const float cr = gi * pr, ci = gi * pim;    // gamma * p (Eqs. 10-11)
             if (jb.log != nullptr && lane == 0) jb.log[it] = (uint16_t)idx;
 
+            // residual: R_w[k,l] -= gamma p W[(k-u) mod S, (l-v) mod S]; slot s
+            // reads duplicated row h + 32 - u + 2s (rows 1 .. 63 of the
+            // table), column (c - v) mod 32: byte offset 256 (h + 32 - u) +
+            // 8 ((c - v) mod 32) + 512 s.  All sixteen reads go out before
+            // the model's lane exchange and are waited for together: issued
+            // a pair at a time behind the exchange (the compiler's order
+            // otherwise), their latency showed through the 2.5 wavefronts
+            // per SIMD that the table's LDS leaves, 3.75 against 3.48 ms
+            // per 1080p frame
+            const int woff = sub_low_byte(hc8 + (8192 - 256 * u), 8 * v);
+            const float2* wrow = reinterpret_cast<const float2*>(
+                reinterpret_cast<const char*>(wtab) + woff);
+            float2 wv[16];
+#pragma unroll
+            for (int s = 0; s < 16; ++s) wv[s] = wrow[64 * s];
             // model: g += gamma p exp(+j 2 pi (u m + v n) / S) on the target
             const int q4 = dot2_u16(u | (v << 16), tmn4);
             const float er = __int_as_float(__builtin_amdgcn_ds_bpermute(q4, tw_re));
@@ -390,16 +405,9 @@ __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int
                 acc = fmaf(ci, ei, acc);
             }
 
-            // residual: R_w[k,l] -= gamma p W[(k-u) mod S, (l-v) mod S]; slot s
-            // reads duplicated row h + 32 - u + 2s (rows 1 .. 63 of the
-            // table), column (c - v) mod 32: byte offset 256 (h + 32 - u) +
-            // 8 ((c - v) mod 32) + 512 s
-            const int woff = sub_low_byte(hc8 + (8192 - 256 * u), 8 * v);
-            const float2* wrow = reinterpret_cast<const float2*>(
-                reinterpret_cast<const char*>(wtab) + woff);
 #pragma unroll
             for (int s = 0; s < 16; ++s) {
-                const float2 w = wrow[64 * s];
+                const float2 w = wv[s];
                 vr[s] = fmaf(-cr, w.x, vr[s]);
                 vr[s] = fmaf(ci, w.y, vr[s]);
                 vi[s] = fmaf(-cr, w.y, vi[s]);
