@@ -171,7 +171,9 @@ FSR_API fsr_status fsr_reconstruct(fsr_context *ctx, const float *image, const u
  * is (nbx - 1) + (r + 1)(nby - 1) + 1 launches (1,825 for 1920 x 1080 at
  * B = 4, L = 14), each with at most min(nby, ceil(nbx / (r + 1))) blocks, so
  * the call is bound by the latency of one block per step rather than by
- * throughput.  S = 32, FSR_DFT_FP32, no flags (FSR_ERR_UNSUPPORTED
+ * throughput; a step of at most 512 blocks (over all frames) runs each
+ * block on four wavefronts, a larger one on one, with bitwise the same
+ * result.  S = 32, FSR_DFT_FP32, no flags (FSR_ERR_UNSUPPORTED
  * otherwise); a reuse_weight outside [0, 1] or NaN is FSR_ERR_INVALID_ARG.
  * Asynchronous on `stream`; capturable into a HIP graph under the same
  * condition as fsr_reconstruct.
