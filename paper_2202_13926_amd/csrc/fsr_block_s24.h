@@ -257,7 +257,8 @@ __device__ __forceinline__ void reconstruct_block_s24(const BlockJob& jb, int B,
             wtab[k * P + l + S] = wv;
         }
         // lane constants kept as computed here
-        const int a8p = opaque(8 * P * a), b8 = opaque(8 * b);
+        // the lane's byte offset 8 P a + 8 b of entry (a, b)
+        const int ab8 = opaque(8 * P * a + 8 * b);
         const int tmn = opaque(tm | (tn << 16));
         const char* wbytes = reinterpret_cast<const char*>(wtab);
         wave_sync();
@@ -316,16 +317,17 @@ __device__ __forceinline__ void reconstruct_block_s24(const BlockJob& jb, int B,
 
             // residual (Eqs. 12, 14-15): bin (k, l) = (a + 8 i, b + 8 j) reads
             // W[(k - u) mod S][(l - v) mod S], table entry
-            // ((a - u + 8 i) mod S, b + 8 j + S - v).  A row offset
-            // 8 P x is wrapped into [0, 8 P S) by a minimum of unsigned
-            // values (x itself when in range, else x -/+ S rows)
-            const int r = a8p - 8 * P * u;
-            const uint32_t r0 = umin((uint32_t)r, (uint32_t)(r + 8 * P * S));
-            const uint32_t r1a = r0 + 64 * P, r2a = r0 + 128 * P;
-            const int cbase = b8 + 8 * (S - v);
-            const int ad0 = (int)r0 + cbase;
-            const int ad1 = (int)umin(r1a, r1a - 8 * P * S) + cbase;
-            const int ad2 = (int)umin(r2a, r2a - 8 * P * S) + cbase;
+            // ((a - u + 8 i) mod S, b + 8 j + S - v).  Byte offset 8 P x + y
+            // of row x, with the column part y = 8 (b + S - v) in [8, 8 P):
+            // a row below 0 or at S and above is wrapped by a minimum of
+            // unsigned values (x itself when in range, else x +/- S rows;
+            // out of range the other one is negative, i.e. huge unsigned)
+            const int uv8 = __builtin_amdgcn_readfirstlane(8 * (S - v) - 8 * P * u);   // scalar
+            const uint32_t y0 = (uint32_t)(ab8 + uv8);
+            const uint32_t ad0 = umin(y0, y0 + 8 * P * S);
+            const uint32_t r1a = ad0 + 64 * P, r2a = ad0 + 128 * P;
+            const uint32_t ad1 = umin(r1a, r1a - 8 * P * S);
+            const uint32_t ad2 = umin(r2a, r2a - 8 * P * S);
             const float2* wrow0 = reinterpret_cast<const float2*>(wbytes + ad0);
             const float2* wrow1 = reinterpret_cast<const float2*>(wbytes + ad1);
             const float2* wrow2 = reinterpret_cast<const float2*>(wbytes + ad2);
