@@ -334,9 +334,13 @@ def test_frames_at_full_size(ctx):
     p = fsr.make_params()
     ti, tm = torch.from_numpy(imgs).to(DEV), torch.from_numpy(masks).to(DEV)
     out = torch.empty_like(ti)
-    fsr.fsr_reconstruct_reuse_frames(ctx, ti, tm, out, p, 0.5)
+    nb = fsr.fsr_num_blocks(imgs.shape[1], imgs.shape[2], p.block)
+    lg = torch.full((len(imgs), nb, p.iterations), -1, dtype=torch.int16, device=DEV)
+    fsr.fsr_reconstruct_reuse_frames(ctx, ti, tm, out, p, 0.5, lg)
     torch.cuda.synchronize()
     got = out.cpu().numpy()
+    logs = lg.cpu().numpy().view(np.uint16)
     for f in range(len(imgs)):
-        ref, _ = run(ctx, imgs[f], masks[f], p, 0.5)
+        ref, ref_log = run(ctx, imgs[f], masks[f], p, 0.5)
         assert np.array_equal(got[f], ref), f"frame {f}"
+        assert np.array_equal(logs[f], ref_log), f"frame {f} log"
