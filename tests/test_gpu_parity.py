@@ -267,8 +267,9 @@ def test_flat_and_clipped_regions(ctx, dft):
     (1 - gamma) per pick while staying a multiple of W, until after about
     20 picks FP32 rounding, not the method, sets the remaining decisions
     (FP64 keeps it exact far longer).  Those late picks carry coefficients
-    of 1e-6 of the first one, so the output still matches; the decision
-    bar is applied to the other blocks."""
+    of 1e-6 of the first one, so the output still matches; the strict
+    decision bar is applied to the other blocks, and every block, white ones
+    included, is held to its resolvable decisions (tests/decisions.py)."""
     announce(f"flat and clipped regions, dft {dft}")
     H, W = 96, 120
     img = synth.make_image(H, W, 77)
@@ -277,13 +278,18 @@ def test_flat_and_clipped_regions(ctx, dft):
     mask = synth.quarter_mask(H, W, 78)
     img32 = img.astype(np.float32)
     g, gl = run_gpu(ctx, img32, mask, fsr.make_params(iterations=60, dft=dft))
-    o, ol, _ = oracle.reconstruct(img32.astype(np.float64), mask, 60, log=True)
+    o, ol, _, (obj, sep) = oracle.reconstruct(img32.astype(np.float64), mask, 60, log=True,
+                                              separations=True)
     nbx = W // 4
     bx = np.arange(len(gl)) % nbx
     black = bx * 4 + 18 <= 40            # support entirely in the black band
     white = bx * 4 - 14 >= 80            # support entirely in the white band
     rep = parity_report(img32, mask, g, o, gl[~white], ol[~white])
     assert_parity(rep, f"flat regions dft{dft}")
+    assert_decisions(gl, ol, obj, sep, f"flat regions dft{dft}, every block")
+    dec_white = decision_report(gl[white], ol[white], obj[white], sep[white])
+    assert dec_white["prefix_decisions"] >= 10 * int(white.sum()), dec_white
+    assert dec_white["prefix_agree"] == 1.0, dec_white
     assert np.all(gl[black] == 0) and np.array_equal(gl[black], ol[black])
     assert np.all(g[:, :22][mask[:, :22] == 0] == 0.0)
     # white supports: the first picks (the DC bin while the residual is
