@@ -26,6 +26,8 @@ if ROOT not in sys.path:
 METRIC = "reconstructed Mpixel/s + p99 frame latency, served/batched vs plain, PSNR gap≤0.05dB"
 WORKLOAD = "fhd_quarter"
 PEAK_FP32_TFLOPS = 157.3       # MI355X FP32 vector peak (256 CU x 2.4 GHz x 256 flop/clk)
+NONPACKED_FP32_TFLOPS = 78.6   # the same with one FP32 FMA per lane and cycle (no packed FP32)
+HBM_PEAK_GB_S = 8000.0         # MI355X HBM3E
 
 
 def algorithmic_flops_per_block(S: int, B: int, iters: int) -> float:
@@ -770,13 +772,22 @@ def main():
                      "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
                      "algorithmic_flop_per_launch": flops,
                      "avg_launch_ms": round(ms_per_step, 5),
-                     "traffic": measured_traffic()},
+                     "traffic": measured_traffic(),
+                     # the same rate against the non-packed FP32 issue rate (this
+                     # build never emits packed FP32), and the HBM side
+                     "frac_of_nonpacked_fp32": round(achieved / NONPACKED_FP32_TFLOPS, 4)},
     }
+    if res["roofline"]["traffic"] is not None:
+        gb_s = res["roofline"]["traffic"] / (ms_per_step * 1e-3) / 1e9
+        res["roofline"]["hbm_gb_s"] = round(gb_s, 2)
+        res["roofline"]["hbm_frac"] = round(gb_s / HBM_PEAK_GB_S, 6)
     if args.support != w.support:
         res["config"]["workload"] += f"; timed at S={args.support} (B=4, L={border}) instead"
         res["roofline"]["kernel"] = "fsr_plain_multi" if args.support == 8 else (
             "fsr_plain_s24" if args.support == 24 else "fsr_plain_sg")
         res["roofline"]["traffic"] = None
+        res["roofline"].pop("hbm_gb_s", None)
+        res["roofline"].pop("hbm_frac", None)
     if args.only_headline:
         ctx.close()
         print(json.dumps(res), flush=True)
