@@ -12,6 +12,7 @@ import pytest
 import oracle
 import synth
 from synth.metrics import parity_report
+from tests.decisions import PREFIX_AGREE, parting_report
 
 torch = pytest.importorskip("torch")
 import paper_2202_13926_amd as fsr  # noqa: E402
@@ -76,7 +77,10 @@ def test_lds_argmax_at_smaller_supports(ctx, B, L):
     """Supports 8, 16, 24 (Fig. 3 spans S = 8 to 32): the LDS tree gives the
     register path's result bitwise (at S = 8 with B <= 4 the register path
     takes eight blocks per wavefront, the LDS variant one), and the oracle
-    pins it on a ragged frame."""
+    pins it on a ragged frame: the decisions FP32 can resolve agree, and
+    the blocks whose decisions all agree match to a code value (a block
+    that parts at a near-tie beyond FP32's resolution carries up to B^2
+    pixels of this small frame with it)."""
     S = B + 2 * L
     print(f"\n[gpu case] LDS argmax at S = {S} (B={B} L={L})", flush=True)
     img = synth.make_image(90, 75, 3100 + S).astype(np.float32)
@@ -86,8 +90,12 @@ def test_lds_argmax_at_smaller_supports(ctx, B, L):
     a, la = run(ctx, img, mask, reg)
     b, lb = run(ctx, img, mask, lds)
     assert np.array_equal(a, b) and np.array_equal(la, lb)
-    o, ol, _ = oracle.reconstruct(img.astype(np.float64), mask, 80, block_size=B, border=L, log=True)
+    o, ol, _, (obj, sep) = oracle.reconstruct(img.astype(np.float64), mask, 80, block_size=B, border=L,
+                                              log=True, separations=True)
     rep = parity_report(img, mask, b, o, lb, ol)
-    print(f"[parity] S={S}: {rep}", flush=True)
-    assert rep["known_bitwise"] and rep["frac_le_1"] >= 0.999 and rep["psnr_gap"] <= 0.05
+    part = parting_report(mask, b, o, lb, ol, obj, sep, B)
+    print(f"[parity] S={S}: {rep} {part}", flush=True)
+    assert rep["known_bitwise"] and rep["psnr_gap"] <= 0.05
     assert rep["argmax_agree"] >= 0.99
+    assert part["prefix_agree"] >= PREFIX_AGREE
+    assert part["agreeing_blocks_frac_le_1"] >= 0.999
