@@ -27,6 +27,8 @@
 // second is transformed.
 #pragma once
 
+#include <type_traits>
+
 #include "fsr_device.h"
 #include "fsr_internal.h"
 #include "fsr_mfma.h"
@@ -304,7 +306,11 @@ __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int
         // lane i of tw_re/tw_im holds t32[i & 31] for the target model's
         // phases; ds_bpermute reads lane (address / 4) mod 64, so the byte
         // address 4 q needs no reduction mod 32
-        const int tw_re = __float_as_int(kTw.re[c]), tw_im = __float_as_int(kTw.im[c]);
+        const int tw_re = opaque(__float_as_int(kTw.re[c])), tw_im = opaque(__float_as_int(kTw.im[c]));
+        // the loads of the loop's constants complete here, not at their first
+        // use inside the loop (which would put their waits in the loop body)
+#pragma unroll
+        for (int s = 0; s < 16; ++s) wf[s] = __int_as_float(opaque(__float_as_int(wf[s])));
         // loop-invariant lane constants: the target pixel's (4 m, 4 n) packed
         // for the phase's bpermute byte address 4 (u m + v n), and the LDS
         // byte offset 256 h + 8 c of the lane's entry (h, c) in W
@@ -323,97 +329,105 @@ __device__ __forceinline__ void reconstruct_block(const BlockJob& jb, int B, int
             vi[s] = xi[s];
         }
 
-        for (int it = 0; it < iters; ++it) {
-            // objective (Eq. 16) as an argmax key: the IEEE bits of the
-            // non-negative float32 objective (so unsigned order is float
-            // order) with the 4 lowest mantissa bits replaced by 15 - slot.
-            // Objectives that agree to 2^-19 relative tie, and ties go to the
-            // smaller slot, then (below) to the lower lane: the smaller bin.
-            int idx;
-            if constexpr (kArgmax == kArgmaxWave) {
-                uint32_t lmax = 0;
+        // the loop comes in two copies, with and without the argmax log, so
+        // that the one without carries no per-iteration branch for it
+        auto iterate = [&](auto with_log) {
+            for (int it = 0; it < iters; ++it) {
+                // objective (Eq. 16) as an argmax key: the IEEE bits of the
+                // non-negative float32 objective (so unsigned order is float
+                // order) with the 4 lowest mantissa bits replaced by 15 - slot.
+                // Objectives that agree to 2^-19 relative tie, and ties go to the
+                // smaller slot, then (below) to the lower lane: the smaller bin.
+                int idx;
+                if constexpr (kArgmax == kArgmaxWave) {
+                    uint32_t lmax = 0;
 #pragma unroll
-                for (int s = 0; s < 16; ++s) {
-                    const float e = fmaf(vr[s], vr[s], vi[s] * vi[s]);
-                    const uint32_t key = (__float_as_uint(e * wf[s]) & 0xFFFFFFF0u) | (uint32_t)(15 - s);
-                    lmax = umax(lmax, key);
-                }
-                const uint32_t mx = wave_max_u32(lmax);
-                const int ln = (int)__builtin_ctzll(ballot(lmax == mx));
-                idx = 64 * (15 - (int)(mx & 15u)) + ln;
-            } else {
+                    for (int s = 0; s < 16; ++s) {
+                        const float e = fmaf(vr[s], vr[s], vi[s] * vi[s]);
+                        const uint32_t key = (__float_as_uint(e * wf[s]) & 0xFFFFFFF0u) | (uint32_t)(15 - s);
+                        lmax = umax(lmax, key);
+                    }
+                    const uint32_t mx = wave_max_u32(lmax);
+                    const int ln = (int)__builtin_ctzll(ballot(lmax == mx));
+                    idx = 64 * (15 - (int)(mx & 15u)) + ln;
+                } else {
 #pragma unroll
-                for (int s = 0; s < 16; ++s) {
-                    const float e = fmaf(vr[s], vr[s], vi[s] * vi[s]);
-                    const uint32_t key = (__float_as_uint(e * wf[s]) & 0xFFFFFFF0u) | (uint32_t)(15 - s);
-                    argmax_lds[64 * s + lane] = make_uint2(key, (uint32_t)(64 * s + lane));
-                }
-                wave_sync();
-                // halve 1024 -> 64 entries, each lane owning entries lane + 64 j
-#pragma unroll
-                for (int half = kBins / 2; half >= 64; half >>= 1) {
-#pragma unroll
-                    for (int j = 0; j < half / 64; ++j) {
-                        const int e = lane + 64 * j;
-                        argmax_lds[e] = better_pair(argmax_lds[e], argmax_lds[e + half]);
+                    for (int s = 0; s < 16; ++s) {
+                        const float e = fmaf(vr[s], vr[s], vi[s] * vi[s]);
+                        const uint32_t key = (__float_as_uint(e * wf[s]) & 0xFFFFFFF0u) | (uint32_t)(15 - s);
+                        argmax_lds[64 * s + lane] = make_uint2(key, (uint32_t)(64 * s + lane));
                     }
                     wave_sync();
+                    // halve 1024 -> 64 entries, each lane owning entries lane + 64 j
+#pragma unroll
+                    for (int half = kBins / 2; half >= 64; half >>= 1) {
+#pragma unroll
+                        for (int j = 0; j < half / 64; ++j) {
+                            const int e = lane + 64 * j;
+                            argmax_lds[e] = better_pair(argmax_lds[e], argmax_lds[e + half]);
+                        }
+                        wave_sync();
+                    }
+                    // 64 -> 1 with a shrinking set of lanes
+#pragma unroll
+                    for (int half = 32; half >= 1; half >>= 1) {
+                        if (lane < half) argmax_lds[lane] = better_pair(argmax_lds[lane], argmax_lds[lane + half]);
+                        wave_sync();
+                    }
+                    idx = __builtin_amdgcn_readfirstlane((int)argmax_lds[0].y);
+                    wave_sync();   // the next iteration overwrites the pairs
                 }
-                // 64 -> 1 with a shrinking set of lanes
-#pragma unroll
-                for (int half = 32; half >= 1; half >>= 1) {
-                    if (lane < half) argmax_lds[lane] = better_pair(argmax_lds[lane], argmax_lds[lane + half]);
-                    wave_sync();
+                const int slot = idx >> 6, ln = idx & 63;
+                const float pr = readlane_f(vr[slot], ln);
+                const float pim = readlane_f(vi[slot], ln);
+                const int u = idx >> 5, v = idx & 31;
+                const float cr = gi * pr, ci = gi * pim;    // gamma * p (Eqs. 10-11)
+                if constexpr (decltype(with_log)::value) {
+                    if (lane == 0) jb.log[it] = (uint16_t)idx;
                 }
-                idx = __builtin_amdgcn_readfirstlane((int)argmax_lds[0].y);
-                wave_sync();   // the next iteration overwrites the pairs
-            }
-            const int slot = idx >> 6, ln = idx & 63;
-            const float pr = readlane_f(vr[slot], ln);
-            const float pim = readlane_f(vi[slot], ln);
-            const int u = idx >> 5, v = idx & 31;
-            const float cr = gi * pr, ci = gi * pim;    // gamma * p (Eqs. 10-11)
-            if (jb.log != nullptr && lane == 0) jb.log[it] = (uint16_t)idx;
 
-            // residual: R_w[k,l] -= gamma p W[(k-u) mod S, (l-v) mod S]; slot s
-            // reads duplicated row h + 32 - u + 2s (rows 1 .. 63 of the
-            // table), column (c - v) mod 32: byte offset 256 (h + 32 - u) +
-            // 8 ((c - v) mod 32) + 512 s.  All sixteen reads go out before
-            // the model's lane exchange and are waited for together: issued
-            // a pair at a time behind the exchange (the compiler's order
-            // otherwise), their latency showed through the 2.5 wavefronts
-            // per SIMD that the table's LDS leaves, 3.75 against 3.48 ms
-            // per 1080p frame
-            const int woff = sub_low_byte(hc8 + (8192 - 256 * u), 8 * v);
-            const float2* wrow = reinterpret_cast<const float2*>(
-                reinterpret_cast<const char*>(wtab) + woff);
-            float2 wv[16];
+                // residual: R_w[k,l] -= gamma p W[(k-u) mod S, (l-v) mod S]; slot s
+                // reads duplicated row h + 32 - u + 2s (rows 1 .. 63 of the
+                // table), column (c - v) mod 32: byte offset 256 (h + 32 - u) +
+                // 8 ((c - v) mod 32) + 512 s.  All sixteen reads go out before
+                // the model's lane exchange and are waited for together: issued
+                // a pair at a time behind the exchange (the compiler's order
+                // otherwise), their latency showed through the 2.5 wavefronts
+                // per SIMD that the table's LDS leaves, 3.75 against 3.48 ms
+                // per 1080p frame
+                const int woff = sub_low_byte(hc8 + (8192 - 256 * u), 8 * v);
+                const float2* wrow = reinterpret_cast<const float2*>(
+                    reinterpret_cast<const char*>(wtab) + woff);
+                float2 wv[16];
 #pragma unroll
-            for (int s = 0; s < 16; ++s) wv[s] = wrow[64 * s];
-            // model: g += gamma p exp(+j 2 pi (u m + v n) / S) on the target
-            const int q4 = dot2_u16(u | (v << 16), tmn4);
-            const float er = __int_as_float(__builtin_amdgcn_ds_bpermute(q4, tw_re));
-            const float ei = __int_as_float(__builtin_amdgcn_ds_bpermute(q4, tw_im));
-            if constexpr (kDft == kDftSplitBf16) {
-                // compensated sum of the I model terms
-                const float y = fmaf(cr, er, ci * ei) - acc_comp;
-                const float t = acc + y;
-                acc_comp = (t - acc) - y;
-                acc = t;
-            } else {
-                acc = fmaf(cr, er, acc);
-                acc = fmaf(ci, ei, acc);
-            }
+                for (int s = 0; s < 16; ++s) wv[s] = wrow[64 * s];
+                // model: g += gamma p exp(+j 2 pi (u m + v n) / S) on the target
+                const int q4 = dot2_u16(u | (v << 16), tmn4);
+                const float er = __int_as_float(__builtin_amdgcn_ds_bpermute(q4, tw_re));
+                const float ei = __int_as_float(__builtin_amdgcn_ds_bpermute(q4, tw_im));
+                if constexpr (kDft == kDftSplitBf16) {
+                    // compensated sum of the I model terms
+                    const float y = fmaf(cr, er, ci * ei) - acc_comp;
+                    const float t = acc + y;
+                    acc_comp = (t - acc) - y;
+                    acc = t;
+                } else {
+                    acc = fmaf(cr, er, acc);
+                    acc = fmaf(ci, ei, acc);
+                }
 
 #pragma unroll
-            for (int s = 0; s < 16; ++s) {
-                const float2 w = wv[s];
-                vr[s] = fmaf(-cr, w.x, vr[s]);
-                vr[s] = fmaf(ci, w.y, vr[s]);
-                vi[s] = fmaf(-cr, w.y, vi[s]);
-                vi[s] = fmaf(-ci, w.x, vi[s]);
+                for (int s = 0; s < 16; ++s) {
+                    const float2 w = wv[s];
+                    vr[s] = fmaf(-cr, w.x, vr[s]);
+                    vr[s] = fmaf(ci, w.y, vr[s]);
+                    vi[s] = fmaf(-cr, w.y, vi[s]);
+                    vi[s] = fmaf(-ci, w.x, vi[s]);
+                }
             }
-        }
+        };
+        if (jb.log != nullptr) iterate(std::true_type{});
+        else iterate(std::false_type{});
         wave_sync();   // the LDS is reused by the next block of a persistent wave
     } else if (jb.log != nullptr) {
         for (int it = lane; it < iters; it += 64) jb.log[it] = (uint16_t)0xFFFF;

@@ -305,6 +305,10 @@ __device__ __forceinline__ void reconstruct_multi(const MultiJob& im, int B, int
     // overwrites the table
     const float2 tw = ftab[S + c];
     const int tw_re = __float_as_int(tw.x), tw_im = __float_as_int(tw.y);
+    // the loads of the loop's constants complete here, not at their first
+    // use inside the loop (which would put their waits in the loop body)
+#pragma unroll
+    for (int s = 0; s < S; ++s) wf[s] = __int_as_float(opaque(__float_as_int(wf[s])));
     wave_sync();
     // W with duplicated rows: entry (R, C) of block b holds W[R mod S][C],
     // at (R NB + b) S + C: the rows of the blocks interleaved, so that one
@@ -321,50 +325,58 @@ __device__ __forceinline__ void reconstruct_multi(const MultiJob& im, int B, int
     const int first4 = opaque(4 * first);
     wave_sync();
 
-    for (int it = 0; it < iters; ++it) {
-        // objective key (Eq. 16): float32 bits, the 4 low mantissa bits
-        // replaced by 15 - k
-        uint32_t lmax = 0;
+    // the loop comes in two copies, with and without the argmax log, so that
+    // the one without carries no per-iteration branch for it
+    auto iterate = [&](auto with_log) {
+        for (int it = 0; it < iters; ++it) {
+            // objective key (Eq. 16): float32 bits, the 4 low mantissa bits
+            // replaced by 15 - k
+            uint32_t lmax = 0;
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const float e = fmaf(xr[s], xr[s], xi[s] * xi[s]);
-            const uint32_t key = (__float_as_uint(e * wf[s]) & 0xFFFFFFF0u) | (uint32_t)(15 - s);
-            lmax = umax(lmax, key);
-        }
-        const uint32_t mx = block_max_u32<S>(lmax);
-        const int v = __builtin_ctz(block_bits<S>(ballot(lmax == mx), first));   // winner's lane
-        const int u = 15 - (int)(mx & 15u);                                       // and row
-        float tr, ti;
-        residual_at<S>(xr, xi, u, tr, ti);
-        const int src = first4 + 4 * v;
-        const float pr = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(tr)));
-        const float pim = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(ti)));
-        const float cr = gi * pr, ci = gi * pim;    // gamma * p (Eqs. 10-11)
-        if (logp != nullptr && c == 0) logp[it] = has_known ? (uint16_t)(u * S + v) : (uint16_t)0xFFFF;
+            for (int s = 0; s < S; ++s) {
+                const float e = fmaf(xr[s], xr[s], xi[s] * xi[s]);
+                const uint32_t key = (__float_as_uint(e * wf[s]) & 0xFFFFFFF0u) | (uint32_t)(15 - s);
+                lmax = umax(lmax, key);
+            }
+            const uint32_t mx = block_max_u32<S>(lmax);
+            const int v = __builtin_ctz(block_bits<S>(ballot(lmax == mx), first));   // winner's lane
+            const int u = 15 - (int)(mx & 15u);                                       // and row
+            float tr, ti;
+            residual_at<S>(xr, xi, u, tr, ti);
+            const int src = first4 + 4 * v;
+            const float pr = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(tr)));
+            const float pim = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(ti)));
+            const float cr = gi * pr, ci = gi * pim;    // gamma * p (Eqs. 10-11)
+            if constexpr (decltype(with_log)::value) {
+                if (logp != nullptr && c == 0) logp[it] = has_known ? (uint16_t)(u * S + v) : (uint16_t)0xFFFF;
+            }
 
-        // model: g += gamma p exp(+j 2 pi (u m + v n) / S) on the target
+            // model: g += gamma p exp(+j 2 pi (u m + v n) / S) on the target
 #pragma unroll
-        for (int t = 0; t < T; ++t) {
-            const int q4 = mad_u24_lanes(u, tm4[t], mad_u24_lanes(v, tn4[t], 0)) & (4 * S - 1);
-            const float er = __int_as_float(__builtin_amdgcn_ds_bpermute(first4 + q4, tw_re));
-            const float ei = __int_as_float(__builtin_amdgcn_ds_bpermute(first4 + q4, tw_im));
-            acc[t] = fmaf(cr, er, acc[t]);
-            acc[t] = fmaf(ci, ei, acc[t]);
-        }
+            for (int t = 0; t < T; ++t) {
+                const int q4 = mad_u24_lanes(u, tm4[t], mad_u24_lanes(v, tn4[t], 0)) & (4 * S - 1);
+                const float er = __int_as_float(__builtin_amdgcn_ds_bpermute(first4 + q4, tw_re));
+                const float ei = __int_as_float(__builtin_amdgcn_ds_bpermute(first4 + q4, tw_im));
+                acc[t] = fmaf(cr, er, acc[t]);
+                acc[t] = fmaf(ci, ei, acc[t]);
+            }
 
-        // residual (Eqs. 12, 14-15): bin (s, c) reads entry (s - u + S,
-        // (c - v) mod S) of its block's table
-        const float2* wrow = reinterpret_cast<const float2*>(
-            wbytes + wb + 8 * ((S - u) * NB * S + ((c - v) & (S - 1))));
+            // residual (Eqs. 12, 14-15): bin (s, c) reads entry (s - u + S,
+            // (c - v) mod S) of its block's table
+            const float2* wrow = reinterpret_cast<const float2*>(
+                wbytes + wb + 8 * ((S - u) * NB * S + ((c - v) & (S - 1))));
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const float2 w = wrow[NB * S * s];
-            xr[s] = fmaf(-cr, w.x, xr[s]);
-            xr[s] = fmaf(ci, w.y, xr[s]);
-            xi[s] = fmaf(-cr, w.y, xi[s]);
-            xi[s] = fmaf(-ci, w.x, xi[s]);
+            for (int s = 0; s < S; ++s) {
+                const float2 w = wrow[NB * S * s];
+                xr[s] = fmaf(-cr, w.x, xr[s]);
+                xr[s] = fmaf(ci, w.y, xr[s]);
+                xi[s] = fmaf(-cr, w.y, xi[s]);
+                xi[s] = fmaf(-ci, w.x, xi[s]);
+            }
         }
-    }
+    };
+    if (im.argmax_log != nullptr) iterate(std::true_type{});
+    else iterate(std::false_type{});
 
     // ---- compose (Sec. II): known pixels copied, unknown pixels Re g
 #pragma unroll

@@ -61,22 +61,25 @@ struct S24 {
     static constexpr int kArgmaxPairs = 1024;     // 576 (key, lane) pairs, padded to 2^10
 };
 
-// Tie codes of this lane's bins (see above) and the slot of each code of a
-// larger-of-pair bin: nibble r of *lmap holds the slot whose code is 6 - r.
-__device__ __forceinline__ void s24_codes(int a, int b, uint32_t (&code)[S24::NS], uint32_t* lmap) {
+// Tie codes of this lane's bins (see above) and the slot of each code:
+// nibble c of the 64-bit map (*map_hi, *map_lo) holds the slot whose code is
+// c (codes no slot of the lane carries hold 0).
+__device__ __forceinline__ void s24_codes(int a, int b, uint32_t (&code)[S24::NS], uint32_t* map_lo,
+                                          uint32_t* map_hi) {
     constexpr int S = S24::S;
     int r = 0;
-    uint32_t m = 0;
+    uint64_t m = 0;
 #pragma unroll
     for (int s = 0; s < S24::NS; ++s) {
         const int k = a + 8 * (s / 3), l = b + 8 * (s % 3);
         const int kc = k ? S - k : 0, lc = l ? S - l : 0;
         const bool larger = k * S + l > kc * S + lc;
         code[s] = larger ? (uint32_t)(6 - r) : (uint32_t)(15 - s);
-        m |= larger ? (uint32_t)s << (4 * r) : 0u;
+        m |= (uint64_t)s << (4 * code[s]);
         r += larger ? 1 : 0;
     }
-    *lmap = m;
+    *map_lo = (uint32_t)m;
+    *map_hi = (uint32_t)(m >> 32);
 }
 
 // kPersistent as in the other block routines (the caller loops over blocks).
@@ -244,8 +247,12 @@ __device__ __forceinline__ void reconstruct_block_s24(const BlockJob& jb, int B,
         // table overwrites the DFT table
         const float2 tw = ftab[S + (lane % S)];
         const int tw_re = __float_as_int(tw.x), tw_im = __float_as_int(tw.y);
-        uint32_t code[NS], lmap;
-        s24_codes(a, b, code, &lmap);
+        uint32_t code[NS], map_lo, map_hi;
+        s24_codes(a, b, code, &map_lo, &map_hi);
+        // the loads of the loop's constants complete here, not at their first
+        // use inside the loop (which would put their waits in the loop body)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) wf[s] = __int_as_float(opaque(__float_as_int(wf[s])));
         wave_sync();   // every lane has read the spectrum and the table
         // W, rows and columns duplicated
         float2* wtab = reinterpret_cast<float2*>(lds);
@@ -263,95 +270,104 @@ __device__ __forceinline__ void reconstruct_block_s24(const BlockJob& jb, int B,
         const char* wbytes = reinterpret_cast<const char*>(wtab);
         wave_sync();
 
-        for (int it = 0; it < iters; ++it) {
-            // objective (Eq. 16) as an argmax key: the float32 bits with the
-            // 4 low mantissa bits replaced by the bin's tie code
-            uint32_t key[NS];
+        // the loop comes in two copies, with and without the argmax log, so
+        // that the one without carries no per-iteration branch for it
+        auto iterate = [&](auto with_log) {
+            for (int it = 0; it < iters; ++it) {
+                // objective (Eq. 16) as an argmax key: the float32 bits with the
+                // 4 low mantissa bits replaced by the bin's tie code
+                uint32_t key[NS];
 #pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                const float e = fmaf(xr[s], xr[s], xi[s] * xi[s]);
-                key[s] = (__float_as_uint(e * wf[s]) & 0xFFFFFFF0u) | code[s];
-            }
-            uint32_t mx;
-            int ln;
-            if constexpr (kArgmax == kArgmaxWave) {
-                uint32_t lmax = 0;
+                for (int s = 0; s < NS; ++s) {
+                    const float e = fmaf(xr[s], xr[s], xi[s] * xi[s]);
+                    key[s] = (__float_as_uint(e * wf[s]) & 0xFFFFFFF0u) | code[s];
+                }
+                uint32_t mx;
+                int ln;
+                if constexpr (kArgmax == kArgmaxWave) {
+                    uint32_t lmax = 0;
 #pragma unroll
-                for (int s = 0; s < NS; ++s) lmax = umax(lmax, key[s]);
-                mx = wave_max_u32(lmax);
-                ln = (int)__builtin_ctzll(ballot(lmax == mx));
-            } else {
+                    for (int s = 0; s < NS; ++s) lmax = umax(lmax, key[s]);
+                    mx = wave_max_u32(lmax);
+                    ln = (int)__builtin_ctzll(ballot(lmax == mx));
+                } else {
 #pragma unroll
-                for (int s = 0; s < NS; ++s) argmax_lds[64 * s + lane] = make_uint2(key[s], (uint32_t)lane);
+                    for (int s = 0; s < NS; ++s) argmax_lds[64 * s + lane] = make_uint2(key[s], (uint32_t)lane);
 #pragma unroll
-                for (int e = 64 * NS; e < S24::kArgmaxPairs; e += 64)
-                    argmax_lds[e + lane] = make_uint2(0u, 0xFFFFFFFFu);
-                wave_sync();
+                    for (int e = 64 * NS; e < S24::kArgmaxPairs; e += 64)
+                        argmax_lds[e + lane] = make_uint2(0u, 0xFFFFFFFFu);
+                    wave_sync();
 #pragma unroll
-                for (int half = S24::kArgmaxPairs / 2; half >= 64; half >>= 1) {
+                    for (int half = S24::kArgmaxPairs / 2; half >= 64; half >>= 1) {
 #pragma unroll
-                    for (int j = 0; j < half / 64; ++j) {
-                        const int e = lane + 64 * j;
-                        argmax_lds[e] = better_pair(argmax_lds[e], argmax_lds[e + half]);
+                        for (int j = 0; j < half / 64; ++j) {
+                            const int e = lane + 64 * j;
+                            argmax_lds[e] = better_pair(argmax_lds[e], argmax_lds[e + half]);
+                        }
+                        wave_sync();
                     }
-                    wave_sync();
+#pragma unroll
+                    for (int half = 32; half >= 1; half >>= 1) {
+                        if (lane < half) argmax_lds[lane] = better_pair(argmax_lds[lane], argmax_lds[lane + half]);
+                        wave_sync();
+                    }
+                    mx = (uint32_t)__builtin_amdgcn_readfirstlane((int)argmax_lds[0].x);
+                    ln = __builtin_amdgcn_readfirstlane((int)argmax_lds[0].y);
+                    wave_sync();   // the next iteration overwrites the pairs
                 }
-#pragma unroll
-                for (int half = 32; half >= 1; half >>= 1) {
-                    if (lane < half) argmax_lds[lane] = better_pair(argmax_lds[lane], argmax_lds[lane + half]);
-                    wave_sync();
+                // the winner's slot from its code, through the winning lane's map
+                const int cw = (int)(mx & 15u);
+                const uint64_t wmap = (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)map_lo, ln) |
+                                      (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)map_hi, ln) << 32;
+                const int slot = (int)((wmap >> (4 * cw)) & 15u);
+                const int u = (ln >> 3) + 8 * (slot / 3), v = (ln & 7) + 8 * (slot % 3);
+                const float pr = readlane_f(xr[slot], ln);
+                const float pim = readlane_f(xi[slot], ln);
+                const float cr = gi * pr, ci = gi * pim;    // gamma * p (Eqs. 10-11)
+                if constexpr (decltype(with_log)::value) {
+                    if (lane == 0) jb.log[it] = (uint16_t)(u * S + v);
                 }
-                mx = (uint32_t)__builtin_amdgcn_readfirstlane((int)argmax_lds[0].x);
-                ln = __builtin_amdgcn_readfirstlane((int)argmax_lds[0].y);
-                wave_sync();   // the next iteration overwrites the pairs
-            }
-            // the winner's slot from its code
-            const int cw = (int)(mx & 15u);
-            const uint32_t lm = (uint32_t)__builtin_amdgcn_readlane((int)lmap, ln);
-            const int slot = cw >= 7 ? 15 - cw : (int)((lm >> (4 * (6 - cw))) & 15u);
-            const int u = (ln >> 3) + 8 * (slot / 3), v = (ln & 7) + 8 * (slot % 3);
-            const float pr = readlane_f(xr[slot], ln);
-            const float pim = readlane_f(xi[slot], ln);
-            const float cr = gi * pr, ci = gi * pim;    // gamma * p (Eqs. 10-11)
-            if (jb.log != nullptr && lane == 0) jb.log[it] = (uint16_t)(u * S + v);
 
-            // residual (Eqs. 12, 14-15): bin (k, l) = (a + 8 i, b + 8 j) reads
-            // W[(k - u) mod S][(l - v) mod S], table entry
-            // ((a - u + 8 i) mod S, b + 8 j + S - v).  Byte offset 8 P x + y
-            // of row x, with the column part y = 8 (b + S - v) in [8, 8 P):
-            // a row below 0 or at S and above is wrapped by a minimum of
-            // unsigned values (x itself when in range, else x +/- S rows;
-            // out of range the other one is negative, i.e. huge unsigned)
-            const int uv8 = __builtin_amdgcn_readfirstlane(8 * (S - v) - 8 * P * u);   // scalar
-            const uint32_t y0 = (uint32_t)(ab8 + uv8);
-            const uint32_t ad0 = umin(y0, y0 + 8 * P * S);
-            const uint32_t r1a = ad0 + 64 * P, r2a = ad0 + 128 * P;
-            const uint32_t ad1 = umin(r1a, r1a - 8 * P * S);
-            const uint32_t ad2 = umin(r2a, r2a - 8 * P * S);
-            const float2* wrow0 = reinterpret_cast<const float2*>(wbytes + ad0);
-            const float2* wrow1 = reinterpret_cast<const float2*>(wbytes + ad1);
-            const float2* wrow2 = reinterpret_cast<const float2*>(wbytes + ad2);
-            const float2* wrows[3] = {wrow0, wrow1, wrow2};
-            // the reads go out before the model's lane exchange, so that the
-            // two wait together
-            float2 w[NS];
+                // residual (Eqs. 12, 14-15): bin (k, l) = (a + 8 i, b + 8 j) reads
+                // W[(k - u) mod S][(l - v) mod S], table entry
+                // ((a - u + 8 i) mod S, b + 8 j + S - v).  Byte offset 8 P x + y
+                // of row x, with the column part y = 8 (b + S - v) in [8, 8 P):
+                // a row below 0 or at S and above is wrapped by a minimum of
+                // unsigned values (x itself when in range, else x +/- S rows;
+                // out of range the other one is negative, i.e. huge unsigned)
+                const int uv8 = __builtin_amdgcn_readfirstlane(8 * (S - v) - 8 * P * u);   // scalar
+                const uint32_t y0 = (uint32_t)(ab8 + uv8);
+                const uint32_t ad0 = umin(y0, y0 + 8 * P * S);
+                const uint32_t r1a = ad0 + 64 * P, r2a = ad0 + 128 * P;
+                const uint32_t ad1 = umin(r1a, r1a - 8 * P * S);
+                const uint32_t ad2 = umin(r2a, r2a - 8 * P * S);
+                const float2* wrow0 = reinterpret_cast<const float2*>(wbytes + ad0);
+                const float2* wrow1 = reinterpret_cast<const float2*>(wbytes + ad1);
+                const float2* wrow2 = reinterpret_cast<const float2*>(wbytes + ad2);
+                const float2* wrows[3] = {wrow0, wrow1, wrow2};
+                // the reads go out before the model's lane exchange, so that the
+                // two wait together
+                float2 w[NS];
 #pragma unroll
-            for (int s = 0; s < NS; ++s) w[s] = wrows[s / 3][8 * (s % 3)];
-            // model: g += gamma p exp(+j 2 pi (u m + v n) / S) on the target
-            const int q4 = 4 * mod_small<S>(dot2_u16(u | (v << 16), tmn));
-            const float er = __int_as_float(__builtin_amdgcn_ds_bpermute(q4, tw_re));
-            const float ei = __int_as_float(__builtin_amdgcn_ds_bpermute(q4, tw_im));
-            acc = fmaf(cr, er, acc);
-            acc = fmaf(ci, ei, acc);
+                for (int s = 0; s < NS; ++s) w[s] = wrows[s / 3][8 * (s % 3)];
+                // model: g += gamma p exp(+j 2 pi (u m + v n) / S) on the target
+                const int q4 = 4 * mod_small<S>(dot2_u16(u | (v << 16), tmn));
+                const float er = __int_as_float(__builtin_amdgcn_ds_bpermute(q4, tw_re));
+                const float ei = __int_as_float(__builtin_amdgcn_ds_bpermute(q4, tw_im));
+                acc = fmaf(cr, er, acc);
+                acc = fmaf(ci, ei, acc);
 
 #pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                xr[s] = fmaf(-cr, w[s].x, xr[s]);
-                xr[s] = fmaf(ci, w[s].y, xr[s]);
-                xi[s] = fmaf(-cr, w[s].y, xi[s]);
-                xi[s] = fmaf(-ci, w[s].x, xi[s]);
+                for (int s = 0; s < NS; ++s) {
+                    xr[s] = fmaf(-cr, w[s].x, xr[s]);
+                    xr[s] = fmaf(ci, w[s].y, xr[s]);
+                    xi[s] = fmaf(-cr, w[s].y, xi[s]);
+                    xi[s] = fmaf(-ci, w[s].x, xi[s]);
+                }
             }
-        }
+        };
+        if (jb.log != nullptr) iterate(std::true_type{});
+        else iterate(std::false_type{});
         wave_sync();   // the LDS is reused by the next block of a persistent wave
     } else if (jb.log != nullptr) {
         for (int it = lane; it < iters; it += 64) jb.log[it] = (uint16_t)0xFFFF;

@@ -335,6 +335,10 @@ __device__ __forceinline__ void reconstruct_block_sg(const BlockJob& jb, int B, 
         // read before W overwrites the table
         const float2 tw = ftab[S + (lane % S)];
         const int tw_re = __float_as_int(tw.x), tw_im = __float_as_int(tw.y);
+        // the loads of the loop's constants complete here, not at their first
+        // use inside the loop (which would put their waits in the loop body)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) wf[s] = __int_as_float(opaque(__float_as_int(wf[s])));
         wave_sync();
         // W with duplicated rows (and columns when kFullDup): entry (R, C)
         // holds W[R mod S][C mod S]
@@ -365,112 +369,120 @@ __device__ __forceinline__ void reconstruct_block_sg(const BlockJob& jb, int B, 
         const char* wbytes = reinterpret_cast<const char*>(wtab);
         wave_sync();
 
-        for (int it = 0; it < iters; ++it) {
-            // objective key (Eq. 16), as in the S = 32 kernel: float32 bits
-            // with the 4 low mantissa bits replaced by 15 - slot
-            int slot, ln;
-            if constexpr (kArgmax == kArgmaxWave) {
-                uint32_t lmax = 0;
+        // the loop comes in two copies, with and without the argmax log, so
+        // that the one without carries no per-iteration branch for it
+        auto iterate = [&](auto with_log) {
+            for (int it = 0; it < iters; ++it) {
+                // objective key (Eq. 16), as in the S = 32 kernel: float32 bits
+                // with the 4 low mantissa bits replaced by 15 - slot
+                int slot, ln;
+                if constexpr (kArgmax == kArgmaxWave) {
+                    uint32_t lmax = 0;
 #pragma unroll
-                for (int s = 0; s < NS; ++s) {
-                    const float e = fmaf(xr[s], xr[s], xi[s] * xi[s]);
-                    const uint32_t key = (__float_as_uint(e * wf[s]) & 0xFFFFFFF0u) | (uint32_t)(15 - s);
-                    lmax = umax(lmax, key);
-                }
-                if (!active) lmax = 0;   // real keys carry a slot code >= 4
-                const uint32_t mx = wave_max_u32(lmax);
-                ln = (int)__builtin_ctzll(ballot(lmax == mx));
-                slot = 15 - (int)(mx & 15u);
-            } else {
-                constexpr int kPairs = sg_argmax_pairs<S>();
-#pragma unroll
-                for (int s = 0; s < NS; ++s) {
-                    const float e = fmaf(xr[s], xr[s], xi[s] * xi[s]);
-                    const uint32_t key = (__float_as_uint(e * wf[s]) & 0xFFFFFFF0u) | (uint32_t)(15 - s);
-                    argmax_lds[64 * s + lane] = make_uint2(active ? key : 0u, (uint32_t)(64 * s + lane));
-                }
-#pragma unroll
-                for (int e = 64 * NS; e < kPairs; e += 64) argmax_lds[e + lane] = make_uint2(0u, 0xFFFFFFFFu);
-                wave_sync();
-#pragma unroll
-                for (int half = kPairs / 2; half >= 64; half >>= 1) {
-#pragma unroll
-                    for (int j = 0; j < half / 64; ++j) {
-                        const int e = lane + 64 * j;
-                        argmax_lds[e] = better_pair(argmax_lds[e], argmax_lds[e + half]);
+                    for (int s = 0; s < NS; ++s) {
+                        const float e = fmaf(xr[s], xr[s], xi[s] * xi[s]);
+                        const uint32_t key = (__float_as_uint(e * wf[s]) & 0xFFFFFFF0u) | (uint32_t)(15 - s);
+                        lmax = umax(lmax, key);
                     }
-                    wave_sync();
-                }
+                    if (!active) lmax = 0;   // real keys carry a slot code >= 4
+                    const uint32_t mx = wave_max_u32(lmax);
+                    ln = (int)__builtin_ctzll(ballot(lmax == mx));
+                    slot = 15 - (int)(mx & 15u);
+                } else {
+                    constexpr int kPairs = sg_argmax_pairs<S>();
 #pragma unroll
-                for (int half = 32; half >= 1; half >>= 1) {
-                    if (lane < half) argmax_lds[lane] = better_pair(argmax_lds[lane], argmax_lds[lane + half]);
+                    for (int s = 0; s < NS; ++s) {
+                        const float e = fmaf(xr[s], xr[s], xi[s] * xi[s]);
+                        const uint32_t key = (__float_as_uint(e * wf[s]) & 0xFFFFFFF0u) | (uint32_t)(15 - s);
+                        argmax_lds[64 * s + lane] = make_uint2(active ? key : 0u, (uint32_t)(64 * s + lane));
+                    }
+#pragma unroll
+                    for (int e = 64 * NS; e < kPairs; e += 64) argmax_lds[e + lane] = make_uint2(0u, 0xFFFFFFFFu);
                     wave_sync();
+#pragma unroll
+                    for (int half = kPairs / 2; half >= 64; half >>= 1) {
+#pragma unroll
+                        for (int j = 0; j < half / 64; ++j) {
+                            const int e = lane + 64 * j;
+                            argmax_lds[e] = better_pair(argmax_lds[e], argmax_lds[e + half]);
+                        }
+                        wave_sync();
+                    }
+#pragma unroll
+                    for (int half = 32; half >= 1; half >>= 1) {
+                        if (lane < half) argmax_lds[lane] = better_pair(argmax_lds[lane], argmax_lds[lane + half]);
+                        wave_sync();
+                    }
+                    const int pos = __builtin_amdgcn_readfirstlane((int)argmax_lds[0].y);
+                    wave_sync();   // the next iteration overwrites the pairs
+                    slot = pos >> 6;
+                    ln = pos & 63;
                 }
-                const int pos = __builtin_amdgcn_readfirstlane((int)argmax_lds[0].y);
-                wave_sync();   // the next iteration overwrites the pairs
-                slot = pos >> 6;
-                ln = pos & 63;
-            }
-            const int u = G * slot + ln / S, v = ln % S;
-            const int idx = u * S + v;
-            // the winner's slot is uniform: with few slots, branch on it
-            // (scalar) and read two fixed registers instead of selecting
-            // among the slots on the vector ALUs; with many, the compiler's
-            // relative move is cheaper than the branches
-            float pr = 0.0f, pim = 0.0f;
-            if constexpr (NS <= 4) {
+                const int u = G * slot + ln / S, v = ln % S;
+                const int idx = u * S + v;
+                // the winner's slot is uniform: with few slots, branch on it
+                // (scalar) and read two fixed registers instead of selecting
+                // among the slots on the vector ALUs; with many, the compiler's
+                // relative move is cheaper than the branches
+                float pr = 0.0f, pim = 0.0f;
+                if constexpr (NS <= 4) {
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) {
+                        if (slot == s) {
+                            pr = readlane_f(xr[s], ln);
+                            pim = readlane_f(xi[s], ln);
+                        }
+                    }
+                } else {
+                    pr = readlane_f(xr[slot], ln);
+                    pim = readlane_f(xi[slot], ln);
+                }
+                const float cr = gi * pr, ci = gi * pim;    // gamma * p (Eqs. 10-11)
+                if constexpr (decltype(with_log)::value) {
+                    if (lane == 0) jb.log[it] = (uint16_t)idx;
+                }
+
+                // model: g += gamma p exp(+j 2 pi (u m + v n) / S) on the target.
+                // Lane i holds F[1][i mod S]; ds_bpermute reads
+                // lane (address / 4) mod 64, so for S dividing 64 the byte
+                // address 4 q needs no reduction mod S
+                int q4;
+                if constexpr (64 % S == 0) q4 = dot2_u16(u | (v << 16), tmn);
+                else q4 = 4 * mod_small<S>(dot2_u16(u | (v << 16), tmn));
+                const float er = __int_as_float(__builtin_amdgcn_ds_bpermute(q4, tw_re));
+                const float ei = __int_as_float(__builtin_amdgcn_ds_bpermute(q4, tw_im));
+                acc = fmaf(cr, er, acc);
+                acc = fmaf(ci, ei, acc);
+
+                // residual (Eqs. 12, 14-15): bin (G s + h, c) reads entry
+                // (G s + h - u + S, c - v + S), i.e. this lane's entry (h, c)
+                // moved by a uniform offset, plus G rows per slot; without
+                // duplicated columns the column (c - v) mod S wraps per lane
+                const float2* wrow;
+                if constexpr (kFullDup) {
+                    wrow = reinterpret_cast<const float2*>(wbytes + lbase + 8 * ((S - u) * P + (S - v)));
+                } else if constexpr ((S & (S - 1)) == 0) {
+                    // the row offset is a multiple of 8 S, the wrapped column
+                    // offset 8 ((c - v) mod S) lies below it
+                    const int col8 = (c8 - 8 * v) & (8 * S - 8);
+                    wrow = reinterpret_cast<const float2*>(wbytes + ((lbase + 8 * (S - u) * P) | col8));
+                } else {
+                    int col = c - v;
+                    col += col < 0 ? S : 0;
+                    wrow = reinterpret_cast<const float2*>(wbytes + lbase + 8 * ((S - u) * P + col));
+                }
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
-                    if (slot == s) {
-                        pr = readlane_f(xr[s], ln);
-                        pim = readlane_f(xi[s], ln);
-                    }
+                    const float2 w = wrow[G * P * s];
+                    xr[s] = fmaf(-cr, w.x, xr[s]);
+                    xr[s] = fmaf(ci, w.y, xr[s]);
+                    xi[s] = fmaf(-cr, w.y, xi[s]);
+                    xi[s] = fmaf(-ci, w.x, xi[s]);
                 }
-            } else {
-                pr = readlane_f(xr[slot], ln);
-                pim = readlane_f(xi[slot], ln);
             }
-            const float cr = gi * pr, ci = gi * pim;    // gamma * p (Eqs. 10-11)
-            if (jb.log != nullptr && lane == 0) jb.log[it] = (uint16_t)idx;
-
-            // model: g += gamma p exp(+j 2 pi (u m + v n) / S) on the target.
-            // Lane i holds F[1][i mod S]; ds_bpermute reads
-            // lane (address / 4) mod 64, so for S dividing 64 the byte
-            // address 4 q needs no reduction mod S
-            int q4;
-            if constexpr (64 % S == 0) q4 = dot2_u16(u | (v << 16), tmn);
-            else q4 = 4 * mod_small<S>(dot2_u16(u | (v << 16), tmn));
-            const float er = __int_as_float(__builtin_amdgcn_ds_bpermute(q4, tw_re));
-            const float ei = __int_as_float(__builtin_amdgcn_ds_bpermute(q4, tw_im));
-            acc = fmaf(cr, er, acc);
-            acc = fmaf(ci, ei, acc);
-
-            // residual (Eqs. 12, 14-15): bin (G s + h, c) reads entry
-            // (G s + h - u + S, c - v + S), i.e. this lane's entry (h, c)
-            // moved by a uniform offset, plus G rows per slot; without
-            // duplicated columns the column (c - v) mod S wraps per lane
-            const float2* wrow;
-            if constexpr (kFullDup) {
-                wrow = reinterpret_cast<const float2*>(wbytes + lbase + 8 * ((S - u) * P + (S - v)));
-            } else if constexpr ((S & (S - 1)) == 0) {
-                // the row offset is a multiple of 8 S, the wrapped column
-                // offset 8 ((c - v) mod S) lies below it
-                const int col8 = (c8 - 8 * v) & (8 * S - 8);
-                wrow = reinterpret_cast<const float2*>(wbytes + ((lbase + 8 * (S - u) * P) | col8));
-            } else {
-                int col = c - v;
-                col += col < 0 ? S : 0;
-                wrow = reinterpret_cast<const float2*>(wbytes + lbase + 8 * ((S - u) * P + col));
-            }
-#pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                const float2 w = wrow[G * P * s];
-                xr[s] = fmaf(-cr, w.x, xr[s]);
-                xr[s] = fmaf(ci, w.y, xr[s]);
-                xi[s] = fmaf(-cr, w.y, xi[s]);
-                xi[s] = fmaf(-ci, w.x, xi[s]);
-            }
-        }
+        };
+        if (jb.log != nullptr) iterate(std::true_type{});
+        else iterate(std::false_type{});
         wave_sync();
     } else if (jb.log != nullptr) {
         for (int it = lane; it < iters; it += 64) jb.log[it] = (uint16_t)0xFFFF;
