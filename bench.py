@@ -216,7 +216,7 @@ def bench_precision(ctx, steps: int = 3):
     return res
 
 
-def bench_argmax_ablation(ctx, img32, mask, params, steps: int = 5):
+def bench_argmax_ablation(ctx, img32, mask, params, steps: int = 20, warmup: int = 3):
     """The paper's comparison (Sec. IV): the same frame and parameters with
     the argmax reduced through an LDS tree instead of in registers."""
     import torch
@@ -246,12 +246,14 @@ def bench_argmax_ablation(ctx, img32, mask, params, steps: int = 5):
     # two rounds, each the register variants first, then the (much longer)
     # shared-memory ones, so that no register timing of the first round
     # follows a long run at a lowered clock; each variant keeps its best round
+    # of as many warm-up and timed launches as the headline leg
     order = sorted(variants, key=lambda k: (k[1] != "register_ms", -1 if k[0] is None else k[0]))
     best = {}
     for _ in range(2):
         for key in order:
             p = variants[key]
-            fsr.fsr_reconstruct(ctx, ti, tm, o, p, None, stream)
+            for _ in range(warmup):
+                fsr.fsr_reconstruct(ctx, ti, tm, o, p, None, stream)
             torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
