@@ -15,12 +15,13 @@
 // of a real tile is bitwise Hermitian without a symmetrisation step (the
 // rounding of a negated operand is the negated rounding).  At S = 16 the two
 // real tiles instead go through one complex transform z = x + j s w, split
-// into the two exactly Hermitian spectra as in the S = 24 and 32 routines:
-// half the sums, 1.01 against 1.06 ms for the 1080p frame at I = 100.
+// into the two exactly Hermitian spectra as in the S = 24 and 32 routines,
+// as two radix-4 x 4 passes (fft16_pass) with one transpose through LDS
+// between them.
 //
 // LDS per wavefront: during the transforms the DFT table (S^2 float2) and
 // a scratch area for the tile and then, over it, the first pass of the DFT
-// (4 S^2 floats);
+// (4 S^2 floats), at S = 16 the passes' exchange and transpose areas;
 // during the iterations W with duplicated rows, and for S <= kFullDupMax
 // duplicated columns too (2S x 2S float2, entry (R, C) = W[R mod S][C mod S],
 // 8 S^2 floats), so that the cyclic shift of Eqs. 14-15 is one uniform
@@ -134,63 +135,80 @@ __device__ __forceinline__ void dft2_sg(const float (&v)[SgShape<S>::NS], float 
     wave_sync();   // the scratch area is reused by the caller
 }
 
-// 2D DFT of the complex tile z = (zr, zi) (slot s = pixel (G s + h, c)) into
-// (zr, zi) (slot s = bin (G s + h, c)), the same direct sums as dft2_sg with
-// a complex first pass.  The tile (S^2 float2) fills the scratch area.
-template <int S>
-__device__ __forceinline__ void dft2_sg_complex(float (&zr)[SgShape<S>::NS], float (&zi)[SgShape<S>::NS],
-                                                const float2* ftab, float* scr, int c, int h, bool active) {
-    constexpr int G = SgShape<S>::G, NS = SgShape<S>::NS;
-    float2* tile = reinterpret_cast<float2*>(scr);   // [m][n], then the first pass [k][n]
-    if (active) {
+// ---- S = 16: the 2D DFT in radix-4 x 4 passes (G = 4 lane groups, NS = 4
+// slots)
+
+// In-place 4-point DFT (W4 = -j) of a lane's four slots, natural order in
+// and out.
+__device__ __forceinline__ void dft4_slots(float (&re)[4], float (&im)[4]) {
+    const float t0r = re[0] + re[2], t0i = im[0] + im[2];
+    const float t1r = re[0] - re[2], t1i = im[0] - im[2];
+    const float t2r = re[1] + re[3], t2i = im[1] + im[3];
+    const float t3r = re[1] - re[3], t3i = im[1] - im[3];
+    re[0] = t0r + t2r; im[0] = t0i + t2i;   // y0
+    re[2] = t0r - t2r; im[2] = t0i - t2i;   // y2
+    re[1] = t1r + t3i; im[1] = t1i - t3r;   // y1 = t1 - j t3
+    re[3] = t1r - t3i; im[3] = t1i + t3r;   // y3 = t1 + j t3
+}
+
+// One 16-point DFT of 16 sequences: slot s of lane (c, h) holds element
+// 4 s + h of sequence c, and on return its output 4 s + h.  With element
+// m = 4 s + h and output k = k1 + 4 k2,
+//   X[k1 + 4 k2] = sum_h W4^(h k2) W16^(h k1) sum_s x[4 s + h] W4^(s k1):
+// the inner sum is a 4-point DFT over the lane's slots; after the twiddle
+// W16^(h k1) (tw_r / tw_i[k1], for this lane's h) lane (c, h) gathers the
+// values of k1 = h from the lanes (c, h'), h' = 0..3, through ex (entry
+// 80 k1 + 16 h + c: the writes of one k1 and the reads of one h' each
+// cover the 64 banks), and a 4-point DFT over h' gives outputs h + 4 k2 in
+// slots k2.
+__device__ __forceinline__ void fft16_pass(float (&re)[4], float (&im)[4], const float (&tw_r)[4],
+                                           const float (&tw_i)[4], float2* ex, int c, int h) {
+    dft4_slots(re, im);
 #pragma unroll
-        for (int s = 0; s < NS; ++s) tile[(G * s + h) * S + c] = make_float2(zr[s], zi[s]);
-    }
+    for (int k1 = 1; k1 < 4; ++k1) cmul(re[k1], im[k1], tw_r[k1], tw_i[k1]);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) ex[80 * k1 + 16 * h + c] = make_float2(re[k1], im[k1]);
     wave_sync();
-    // pass 1 along m: C[k][n] = sum_m z[m][n] F[m][k], k = G s + h, n = c
-    float ar[NS], ai[NS];
 #pragma unroll
-    for (int s = 0; s < NS; ++s) ar[s] = ai[s] = 0.0f;
-#pragma unroll 2
-    for (int m = 0; m < S; ++m) {
-        const float2 z = tile[m * S + c];
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const float2 f = ftab[m * S + G * s + h];
-            ar[s] = fmaf(z.x, f.x, ar[s]);
-            ar[s] = fmaf(-z.y, f.y, ar[s]);
-            ai[s] = fmaf(z.x, f.y, ai[s]);
-            ai[s] = fmaf(z.y, f.x, ai[s]);
-        }
+    for (int g = 0; g < 4; ++g) {
+        const float2 v = ex[80 * h + 16 * g + c];
+        re[g] = v.x;
+        im[g] = v.y;
     }
-    wave_sync();   // every lane has read the tile
-    if (active) {
+    wave_sync();   // every lane has read ex
+    dft4_slots(re, im);
+}
+
+// Entry i (re, im) of a float2 table in global memory.
+__device__ __forceinline__ void table_entry(const float2* tab, int i, float& re, float& im) {
+    const uint64_t v = global_ptr(reinterpret_cast<const uint64_t*>(tab))[i];
+    re = __uint_as_float((uint32_t)v);
+    im = __uint_as_float((uint32_t)(v >> 32));
+}
+
+// Row pitch (float2) of the S = 16 tiles in LDS: the 16 lanes of a row
+// group reading a column start 36 words apart, 32 lanes cover the 64 banks.
+constexpr int kS16Pitch = 18;
+
+// 2D DFT of the complex S = 16 tile z (slot s of lane (c, h) = pixel
+// (4 s + h, c)), along m, then, after a transpose through buf, along n: on
+// return slot s of lane (c, h) holds bin (c, 4 s + h), i.e. the spectrum
+// transposed.  buf holds 304 float2 (the exchange areas' extent).
+__device__ __forceinline__ void fft2_s16(float (&zr)[4], float (&zi)[4], const float (&tw_r)[4],
+                                         const float (&tw_i)[4], float2* buf, int c, int h) {
+    constexpr int P = kS16Pitch;
+    fft16_pass(zr, zi, tw_r, tw_i, buf, c, h);   // slot s: C[4 s + h][c]
 #pragma unroll
-        for (int s = 0; s < NS; ++s) tile[(G * s + h) * S + c] = make_float2(ar[s], ai[s]);
-    }
+    for (int s = 0; s < 4; ++s) buf[(4 * s + h) * P + c] = make_float2(zr[s], zi[s]);
     wave_sync();
-    // pass 2 along n: Z[k][l] = sum_n C[k][n] F[n][l], k = G s + h, l = c
-    float br[NS], bi[NS];
 #pragma unroll
-    for (int s = 0; s < NS; ++s) br[s] = bi[s] = 0.0f;
-#pragma unroll 2
-    for (int n = 0; n < S; ++n) {
-        const float2 f = ftab[n * S + c];
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const float2 a = tile[(G * s + h) * S + n];
-            br[s] = fmaf(a.x, f.x, br[s]);
-            br[s] = fmaf(-a.y, f.y, br[s]);
-            bi[s] = fmaf(a.x, f.y, bi[s]);
-            bi[s] = fmaf(a.y, f.x, bi[s]);
-        }
+    for (int s = 0; s < 4; ++s) {
+        const float2 v = buf[c * P + 4 * s + h];   // C[c][4 s + h]: row c as sequence c
+        zr[s] = v.x;
+        zi[s] = v.y;
     }
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        zr[s] = br[s];
-        zi[s] = bi[s];
-    }
-    wave_sync();   // the scratch area is reused by the caller
+    wave_sync();   // every lane has read the transpose
+    fft16_pass(zr, zi, tw_r, tw_i, buf, c, h);   // slot s: Z[c][4 s + h]
 }
 
 // kPersistent: the caller loops over blocks; as in the S = 32 routine, the
@@ -230,8 +248,9 @@ __device__ __forceinline__ void reconstruct_block_sg(const BlockJob& jb, int B, 
     float2* ftab = reinterpret_cast<float2*>(lds);
     float* scr = lds + 2 * S * S;
 
-    // ---- DFT table into LDS (S^2 float2, the same for every block)
-    {
+    // ---- DFT table into LDS (S^2 float2, the same for every block); the
+    // S = 16 transform takes its few twiddles from global memory instead
+    if constexpr (S != 16) {
         const global_t<const uint64_t>* src = global_ptr(reinterpret_cast<const uint64_t*>(tab.dft_sg));
         uint64_t* dst = reinterpret_cast<uint64_t*>(ftab);
         for (int i = lane; i < S * S; i += 64) dst[i] = src[i];
@@ -292,20 +311,27 @@ __device__ __forceinline__ void reconstruct_block_sg(const BlockJob& jb, int B, 
             const float sc = sbits ? __uint_as_float(sbits) : 1.0f;
 #pragma unroll
             for (int s = 0; s < NS; ++s) xi[s] = wr[s] * sc;
-            dft2_sg_complex<S>(xr, xi, ftab, scr, c, h, active);
-            // X = (Z + conj Z[-k]) / 2, W = (Z - conj Z[-k]) / (2 j s): bins
-            // k and -k read the same pair of values in swapped roles
-            float2* zs = reinterpret_cast<float2*>(scr);
+            // W16^(h k1), k1 = 1..3, from the table's row F[1]
+            float tw_r[4] = {1.0f, 0.0f, 0.0f, 0.0f}, tw_i[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-            for (int s = 0; s < NS; ++s) zs[(G * s + h) * S + c] = make_float2(xr[s], xi[s]);
+            for (int k1 = 1; k1 < 4; ++k1) table_entry(tab.dft_sg, S + ((h * k1) & (S - 1)), tw_r[k1], tw_i[k1]);
+            float2* zs = reinterpret_cast<float2*>(lds);   // the whole area: no table at S = 16
+            fft2_s16(xr, xi, tw_r, tw_i, zs, c, h);       // slot s: Z[c][4 s + h]
+            // X = (Z + conj Z[-k]) / 2, W = (Z - conj Z[-k]) / (2 j s): bins
+            // k and -k read the same pair of values in swapped roles (Z in
+            // natural order at zs[k P + l], P = kS16Pitch)
+            constexpr int P16 = kS16Pitch;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) zs[c * P16 + G * s + h] = make_float2(xr[s], xi[s]);
             wave_sync();
             const float hs = 0.5f / sc;
             const int lm = (S - c) & (S - 1);
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
                 const int km = (S - (G * s + h)) & (S - 1);
-                const float2 zm = zs[km * S + lm];
-                const float ar = xr[s], ai = xi[s];
+                const float2 zo = zs[(G * s + h) * P16 + c];   // this lane's bin
+                const float2 zm = zs[km * P16 + lm];
+                const float ar = zo.x, ai = zo.y;
                 xr[s] = 0.5f * (ar + zm.x);
                 xi[s] = 0.5f * (ai - zm.y);
                 wr[s] = (ai + zm.y) * hs;
@@ -331,10 +357,10 @@ __device__ __forceinline__ void reconstruct_block_sg(const BlockJob& jb, int B, 
         float wf[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) wf[s] = global_ptr(tab.freq_w)[(G * s + h) * S + c];
-        // lane i (< S) of tw_re / tw_im holds F[1][i] = exp(-j 2 pi i / S),
-        // read before W overwrites the table
-        const float2 tw = ftab[S + (lane % S)];
-        const int tw_re = __float_as_int(tw.x), tw_im = __float_as_int(tw.y);
+        // lane i (< S) of tw_re / tw_im holds F[1][i] = exp(-j 2 pi i / S)
+        float twx, twy;
+        table_entry(tab.dft_sg, S + (lane % S), twx, twy);
+        const int tw_re = opaque(__float_as_int(twx)), tw_im = opaque(__float_as_int(twy));
         // the loads of the loop's constants complete here, not at their first
         // use inside the loop (which would put their waits in the loop body)
 #pragma unroll
