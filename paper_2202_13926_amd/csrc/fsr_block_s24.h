@@ -18,13 +18,12 @@
 // slot that is the smaller bin.  A key's code and lane give back its slot.
 //
 // DFT: both real tiles in one complex transform z = (f~ - mu) w + j s w
-// (s a power of two, as in the S = 32 kernel), by direct separable sums
-// against the table F[m][k] = exp(-j 2 pi m k / S) in LDS, then split into
-// the two exactly Hermitian spectra.
+// (s a power of two, as in the S = 32 kernel), two radix-3 x 8 passes
+// (s24_pass) with twiddles from the table F[m][k] = exp(-j 2 pi m k / S) in
+// LDS, then split into the two exactly Hermitian spectra.
 //
-// LDS per wavefront: the DFT table (S^2 float2) and a scratch area (S^2
-// float2: the tile, then the first pass, then the spectrum) during the
-// transforms; during the iterations W with its columns repeated once (24
+// LDS per wavefront: the DFT table (S^2 float2) and a scratch area (the
+// passes' 24 x 25 float2, then the spectrum) during the transforms; during the iterations W with its columns repeated once (24
 // rows of 48 entries, entry (R, C) = W[R][C mod S]) at a row pitch of 52
 // entries, 9.75 KiB.  Slot (i, j) of lane (a, b) reads row (a - u + 8 i)
 // mod S, wrapped per row slot i, and column b + 8 j + S - v, which needs no
@@ -57,7 +56,7 @@ struct S24 {
     static constexpr int kPitch = 52;             // W table: S rows of 2S entries (float2), this pitch
     static constexpr int kTabFloats = 2 * S * S;  // DFT table, then scratch
     static constexpr int kLdsFloats = 2 * S * kPitch;
-    static_assert(2 * kTabFloats <= kLdsFloats, "transforms fit in the W table's space");
+    static_assert(kTabFloats + 2 * 24 * 25 <= kLdsFloats, "transforms fit in the W table's space");
     static constexpr int kArgmaxPairs = 1024;     // 576 (key, lane) pairs, padded to 2^10
 };
 
@@ -80,6 +79,68 @@ __device__ __forceinline__ void s24_codes(int a, int b, uint32_t (&code)[S24::NS
     }
     *map_lo = (uint32_t)m;
     *map_hi = (uint32_t)(m >> 32);
+}
+
+// One 24-point DFT pass over the 24 sequences of one axis, radix 3 x 8:
+// with element x = p + 8 q (p < 8 across lanes, q < 3 in the lane's slots)
+// and output k = k1 + 3 k2 (k1 < 3, k2 < 8),
+//   X[k1 + 3 k2] = sum_p W8^(p k2) W24^(p k1) sum_q x[p + 8 q] W3^(q k1).
+// A 3-point DFT over the lane's slots and the twiddle W24^(p k1) go to buf
+// (entry (8 k1 + p) 25 + sequence: the three k1 groups of a read start 0,
+// 16 and 32 words apart); each output then sums its eight terms over p by
+// Horner's rule in W8^k2, which keeps the natural layout (output k = p + 8 q
+// in the slot of element p + 8 q).  kAlongM: along m (p = a, q = i, the
+// sequence n = b + 8 j), else along n (p = b, q = j, the sequence
+// k = a + 8 i).  ftab is the DFT table, row F[1] = W24^q.
+template <bool kAlongM>
+__device__ __forceinline__ void s24_pass(float (&re)[S24::NS], float (&im)[S24::NS], const float2* ftab,
+                                         float2* buf, int a, int b) {
+    constexpr int S = S24::S, P = 25;
+    constexpr float kH3 = 0.866025403784438647f;   // sin(pi / 3)
+    const int p = kAlongM ? a : b, o = kAlongM ? b : a;
+    const float2 t1 = ftab[S + p], t2 = ftab[S + 2 * p];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const int s0 = kAlongM ? r : 3 * r, ds = kAlongM ? 3 : 1;   // slot of q = 0, step per q
+        const float x0r = re[s0], x0i = im[s0];
+        const float tr = re[s0 + ds] + re[s0 + 2 * ds], ti = im[s0 + ds] + im[s0 + 2 * ds];
+        const float dr = re[s0 + ds] - re[s0 + 2 * ds], di = im[s0 + ds] - im[s0 + 2 * ds];
+        const float hr = fmaf(-0.5f, tr, x0r), hi = fmaf(-0.5f, ti, x0i);
+        float y1r = fmaf(kH3, di, hr), y1i = fmaf(-kH3, dr, hi);    // x0 + W3 x1 + W3^2 x2
+        float y2r = fmaf(-kH3, di, hr), y2i = fmaf(kH3, dr, hi);    // x0 + W3^2 x1 + W3 x2
+        cmul(y1r, y1i, t1.x, t1.y);
+        cmul(y2r, y2i, t2.x, t2.y);
+        const int col = o + 8 * r;
+        buf[p * P + col] = make_float2(x0r + tr, x0i + ti);
+        buf[(8 + p) * P + col] = make_float2(y1r, y1i);
+        buf[(16 + p) * P + col] = make_float2(y2r, y2i);
+    }
+    wave_sync();
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const int k = p + 8 * q, k1 = k % 3, k2 = k / 3;
+        const float2 w = ftab[S + 3 * k2];   // W8^k2
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const float2* col = buf + 8 * k1 * P + o + 8 * r;
+            float xr = col[7 * P].x, xi = col[7 * P].y;
+#pragma unroll
+            for (int pp = 6; pp >= 0; --pp) {
+                const float2 v = col[pp * P];
+                cmul(xr, xi, w.x, w.y);
+                xr += v.x;
+                xi += v.y;
+            }
+            const int s = kAlongM ? 3 * q + r : 3 * r + q;
+            re[s] = xr;
+            im[s] = xi;
+            // no reads of the next sum ahead of this one: 8 reads in flight
+            // instead of 72, which would take the persistent kernels past
+            // 128 VGPRs (three wavefronts per SIMD instead of four)
+            asm volatile("" ::: "memory");
+        }
+    }
+    wave_sync();   // every lane has read buf
 }
 
 // kPersistent as in the other block routines (the caller loops over blocks).
@@ -159,55 +220,15 @@ __device__ __forceinline__ void reconstruct_block_s24(const BlockJob& jb, int B,
         // z = x + j sc w with sc the power of two at or below max |x| (exact)
         const uint32_t sbits = amax & 0x7F800000u;
         const float sc = sbits ? __uint_as_float(sbits) : 1.0f;
-#pragma unroll
-        for (int s = 0; s < NS; ++s) scr[(a + 8 * (s / 3)) * S + b + 8 * (s % 3)] = make_float2(xr[s], wr[s] * sc);
-        wave_sync();
-
-        // pass 1 along m: C[k][n] = sum_m z[m][n] F[m][k], k = a + 8 i, n = b + 8 j
-        float c1r[NS], c1i[NS];
-#pragma unroll
-        for (int s = 0; s < NS; ++s) c1r[s] = c1i[s] = 0.0f;
-#pragma unroll 2
-        for (int m = 0; m < S; ++m) {
-            float2 z[3], f[3];
-#pragma unroll
-            for (int j = 0; j < 3; ++j) z[j] = scr[m * S + b + 8 * j];
-#pragma unroll
-            for (int i = 0; i < 3; ++i) f[i] = ftab[m * S + a + 8 * i];
-#pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                const float2 zz = z[s % 3], ff = f[s / 3];
-                c1r[s] = fmaf(zz.x, ff.x, c1r[s]);
-                c1r[s] = fmaf(-zz.y, ff.y, c1r[s]);
-                c1i[s] = fmaf(zz.x, ff.y, c1i[s]);
-                c1i[s] = fmaf(zz.y, ff.x, c1i[s]);
-            }
-        }
-        wave_sync();   // every lane has read the tile
-#pragma unroll
-        for (int s = 0; s < NS; ++s) scr[(a + 8 * (s / 3)) * S + b + 8 * (s % 3)] = make_float2(c1r[s], c1i[s]);
-        wave_sync();
-        // pass 2 along n: Z[k][l] = sum_n C[k][n] F[n][l], l = b + 8 j
+        // the two passes, radix 3 x 8 (s24_pass), on z = x + j sc w in registers
         float zr[NS], zi[NS];
 #pragma unroll
-        for (int s = 0; s < NS; ++s) zr[s] = zi[s] = 0.0f;
-#pragma unroll 2
-        for (int n = 0; n < S; ++n) {
-            float2 cc[3], f[3];
-#pragma unroll
-            for (int i = 0; i < 3; ++i) cc[i] = scr[(a + 8 * i) * S + n];
-#pragma unroll
-            for (int j = 0; j < 3; ++j) f[j] = ftab[n * S + b + 8 * j];
-#pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                const float2 c2 = cc[s / 3], ff = f[s % 3];
-                zr[s] = fmaf(c2.x, ff.x, zr[s]);
-                zr[s] = fmaf(-c2.y, ff.y, zr[s]);
-                zi[s] = fmaf(c2.x, ff.y, zi[s]);
-                zi[s] = fmaf(c2.y, ff.x, zi[s]);
-            }
+        for (int s = 0; s < NS; ++s) {
+            zr[s] = xr[s];
+            zi[s] = wr[s] * sc;
         }
-        wave_sync();   // every lane has read the first pass
+        s24_pass<true>(zr, zi, ftab, scr, a, b);    // along m: C[k][n]
+        s24_pass<false>(zr, zi, ftab, scr, a, b);   // along n: Z[k][l]
 #pragma unroll
         for (int s = 0; s < NS; ++s) scr[(a + 8 * (s / 3)) * S + b + 8 * (s % 3)] = make_float2(zr[s], zi[s]);
         wave_sync();
