@@ -355,7 +355,7 @@ def bench_multiresolution(ctx, steps: int = 20, warmup: int = 3):
     for the paper's real-time table resolutions (Sec. IV: VGA, SVGA, FHD,
     UHD), the four frames as one batch (tuned batched launch in a graph
     against one launch per frame), and the 1080p frame at every support size
-    this build runs."""
+    the library runs."""
     import torch
 
     import paper_2202_13926_amd as fsr
@@ -699,7 +699,7 @@ def main():
         copy_calibration(args.copy_calibration)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1 "
                                    "(multi-GPU sharding is described in the design notes only)"}))
         sys.exit(2)
     import torch

@@ -47,7 +47,7 @@ extern "C" {
 typedef enum fsr_status {
     FSR_OK = 0,
     FSR_ERR_INVALID_ARG = 1,   /* a pointer, size or parameter is invalid  */
-    FSR_ERR_UNSUPPORTED = 2,   /* valid, but outside what this build runs  */
+    FSR_ERR_UNSUPPORTED = 2,   /* valid, but outside what the library runs */
     FSR_ERR_OUT_OF_MEMORY = 3, /* a device or host allocation failed       */
     FSR_ERR_BUDGET = 4,        /* request exceeds the configured budget    */
     FSR_ERR_HIP = 5,           /* the HIP runtime reported an error        */
@@ -84,7 +84,7 @@ enum {
  *   block >= 1, border >= 0, S = block + 2*border even and <= 32,
  *   iterations >= 0, 0 < rho <= 1, 0 < gamma <= 1 (Sec. II), flags a
  *   combination of FSR_FLAG_*.
- * This build runs S in {8, 16, 24, 32} with block <= 8 (FSR_ERR_UNSUPPORTED
+ * The library runs S in {8, 16, 24, 32} with block <= 8 (FSR_ERR_UNSUPPORTED
  * otherwise), on the one-image, batched and served paths alike;
  * FSR_DFT_SPLIT_BF16 runs S = 32 only; FSR_FLAG_LDS_ARGMAX runs every
  * support on the one-image path.

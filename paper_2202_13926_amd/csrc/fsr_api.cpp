@@ -91,8 +91,8 @@ fsr_status validate_params(const fsr_params* p) {
 fsr_status check_supported(const fsr_params* p) {
     const int S = p->block + 2 * p->border;
     if (S != 8 && S != 16 && S != 24 && S != kS)
-        return fail(FSR_ERR_UNSUPPORTED, "this build runs support sizes 8, 16, 24 and 32 (got %d)", S);
-    if (p->block > 8) return fail(FSR_ERR_UNSUPPORTED, "this build runs block <= 8 (got %d)", p->block);
+        return fail(FSR_ERR_UNSUPPORTED, "the library runs support sizes 8, 16, 24 and 32 (got %d)", S);
+    if (p->block > 8) return fail(FSR_ERR_UNSUPPORTED, "the library runs block <= 8 (got %d)", p->block);
     return FSR_OK;
 }
 

@@ -68,7 +68,7 @@ def test_reconstruct_validates_before_touching_the_device(lib):
     assert _call(lib, fake_ctx, img, msk, ctypes.c_void_p(0x10000 + 64), 8, 8, 8, p) == binding.FSR_ERR_INVALID_ARG
     # out overlapping mask
     assert _call(lib, fake_ctx, img, msk, ctypes.c_void_p(0x20000000 + 8), 8, 8, 8, p) == binding.FSR_ERR_INVALID_ARG
-    # valid but outside this build: support 12 and 20
+    # valid but outside what the library runs: support 12 and 20
     for p_other in (fsr.make_params(block=4, border=4), fsr.make_params(block=4, border=8)):
         assert _call(lib, fake_ctx, img, msk, out, 8, 8, 8, p_other) == binding.FSR_ERR_UNSUPPORTED
     # the smaller supports run with the FP32 DFT only (the LDS argmax flag is
